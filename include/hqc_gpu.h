@@ -1,0 +1,169 @@
+/*
+ * hqc_gpu.h -- C ABI of the gfx950 HQC decryption library (libhqc_gpu.so).
+ *
+ * What it computes: HQC.PKE.Decrypt (Alg. 2 of the OptHQC paper, arXiv
+ * 2512.12904) in batches, with the secret key y:
+ *     m = C.Decode(v + (u * y) restricted to its first n1*n2 bits)
+ * where u * y is the product in GF(2)[X]/(X^n - 1) of Eq. (1), computed as
+ * the XOR of the rotations of u by the support indices of y, and C.Decode
+ * is the concatenated decoder of Sec. II-A: each of the n1 blocks of n2 bits
+ * is decoded as a duplicated RM(1,7) codeword (maximum likelihood, by a
+ * 128-point Walsh-Hadamard transform), then the n1 symbols are decoded as a
+ * shortened Reed-Solomon codeword over GF(2^8) (syndromes, Berlekamp-Massey,
+ * Chien search, Forney) and the k message bytes are returned.  Parameter
+ * sets: Table I (HQC-1, HQC-3, HQC-5).
+ *
+ * Conventions (fixed so that every input, also one beyond the decoding
+ * radius, has one defined output):
+ *   - bit t of a polynomial is bit (t & 63) of 64-bit word (t >> 6);
+ *   - u: ceil(n/64) words per item; bits >= n are ignored;
+ *   - v: n1*n2/64 words per item (v is truncated to n1*n2 bits);
+ *   - y: w uint32 support indices per item, read as the polynomial
+ *     sum_k X^(y_k mod n) (repeated indices cancel);
+ *   - RM block j of the received word is bits [j*n2, (j+1)*n2); copy q of
+ *     the 128-bit RM(1,7) word sits at offset 128*q; byte b encodes as
+ *     bit i = b7 ^ parity(b & i & 0x7F); the decoder takes the smallest
+ *     index among equal-magnitude Hadamard peaks;
+ *   - RS: narrow-sense (roots alpha^1..alpha^2delta, alpha = x, field
+ *     polynomial x^8+x^4+x^3+x^2+1), parity symbols first, message byte t
+ *     at symbol 2*delta + t; corrections are applied without a failure
+ *     check (PKE decryption has no failure output).
+ *   - m_out: k bytes per item.
+ *
+ * Memory: every array argument is DEVICE memory (hipMalloc'd or a torch
+ * CUDA/HIP tensor), except y_host in hqc_keystore_put* and the hqc_params_t /
+ * hqc_segment_t structs themselves, which are host memory read during the
+ * call and not retained.  The caller owns all buffers.  u, v, r must be
+ * 8-byte aligned, y and key_ids 4-byte aligned.
+ *
+ * Execution: calls enqueue work on params->stream (a hipStream_t; NULL means
+ * the null stream) and return; outputs are valid once that stream is
+ * synchronised.  Kernels never branch on or index by secret data except
+ * through data-independent primitives (see the library's design notes).
+ *
+ * Errors: every int-returning call returns HQC_OK or a negative code; on an
+ * error detected before launch nothing is enqueued and nothing is written.
+ * count == 0 is a successful no-op.  HQC_EHIP reports a HIP runtime error,
+ * whose hipError_t is then available from hqc_last_hip_error().
+ */
+#ifndef HQC_GPU_H
+#define HQC_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HQC_OK 0
+#define HQC_EINVAL (-1)   /* bad pointer, alignment, parameter id, flags  */
+#define HQC_ERANGE (-2)   /* count or key id beyond what the call supports */
+#define HQC_EHIP (-3)     /* HIP runtime error (see hqc_last_hip_error)    */
+#define HQC_ENOMEM (-4)   /* device or host allocation failed              */
+
+/* params->flags */
+#define HQC_F_PER_ITEM_LAUNCH 0x1u /* baseline: one kernel launch per item   */
+#define HQC_F_GRAPH 0x2u           /* launch through a cached hipGraph        */
+
+/* Largest count of one call (items are indexed with 32-bit integers). */
+#define HQC_MAX_COUNT ((size_t)1 << 31)
+
+/* Sizes of one parameter set (Table I plus derived word counts). */
+typedef struct hqc_sizes {
+  int32_t param_id; /* 1, 3 or 5 */
+  int32_t n;        /* ring length */
+  int32_t n1, k;    /* RS length and dimension (k = message bytes) */
+  int32_t delta;    /* RS correction radius */
+  int32_t n2;       /* duplicated RM length = 128 * mult */
+  int32_t mult;     /* RM(1,7) copies per block */
+  int32_t w;        /* weight of y */
+  int32_t wr, we;   /* weights of r1, r2 and e (encryption side) */
+  int32_t u_words;  /* uint64 words of u per item = ceil(n / 64) */
+  int32_t v_words;  /* uint64 words of v (or r) per item = n1 * n2 / 64 */
+} hqc_sizes_t;
+
+/* Per-call launch options (host struct, read during the call only). */
+typedef struct hqc_params {
+  int32_t param_id; /* 1, 3 or 5; ignored by the *_mixed calls */
+  uint32_t flags;   /* HQC_F_* */
+  void *stream;     /* hipStream_t, or NULL for the null stream */
+  int32_t grid;     /* persistent workgroups; 0 = chosen by the library */
+  int32_t reserved; /* must be 0 */
+} hqc_params_t;
+
+/* One homogeneous part of a mixed-parameter batch (host struct). */
+typedef struct hqc_segment {
+  int32_t param_id;        /* 1, 3 or 5 */
+  int32_t reserved;        /* must be 0 */
+  size_t count;            /* items in this segment */
+  const uint64_t *u;       /* decrypt: count * u_words; decode: r, count * v_words */
+  const uint64_t *v;       /* decrypt: count * v_words; decode: NULL */
+  const uint32_t *y;       /* decrypt: count * w; decode: NULL */
+  uint8_t *m_out;          /* count * k bytes */
+} hqc_segment_t;
+
+typedef struct hqc_keystore hqc_keystore_t;
+
+/* Fills *out for param_id 1, 3 or 5.  HQC_EINVAL for another id or NULL. */
+int hqc_sizes(int param_id, hqc_sizes_t *out);
+
+/* Alg. 2 on count items of one parameter set: m_out[i] = Decrypt(y[i],
+ * (u[i], v[i])).  The whole batch is one persistent kernel launch (or one
+ * hipGraph launch with HQC_F_GRAPH, or count launches with
+ * HQC_F_PER_ITEM_LAUNCH).  Precondition (not checked on the device): the
+ * arrays hold count items. */
+int hqc_decrypt_batch(const hqc_params_t *params, const uint64_t *u,
+                      const uint64_t *v, const uint32_t *y, uint8_t *m_out,
+                      size_t count);
+
+/* C.Decode only (Sec. II-A): m_out[i] = Decode(r[i]), r: count * v_words.
+ * Equals hqc_decrypt_batch with u = 0. */
+int hqc_decode_batch(const hqc_params_t *params, const uint64_t *r,
+                     uint8_t *m_out, size_t count);
+
+/* Mixed HQC-1/3/5 batches: up to 3 segments (at most one per parameter
+ * set), processed by one persistent launch.  Results are identical to
+ * per-segment hqc_decrypt_batch / hqc_decode_batch calls. */
+int hqc_decrypt_mixed(const hqc_params_t *params, const hqc_segment_t *segs,
+                      int nseg);
+int hqc_decode_mixed(const hqc_params_t *params, const hqc_segment_t *segs,
+                     int nseg);
+
+/* Device-resident secret keys (the y of Alg. 3) for serving.  cap[i] is the
+ * number of key slots for HQC-1, HQC-3, HQC-5 (i = 0, 1, 2).  Slots start
+ * zero (an all-zero y).  The store owns its device memory until destroy. */
+int hqc_keystore_create(hqc_keystore_t **ks, const size_t cap[3]);
+/* Copies w indices from host memory into slot key_id; every index must be
+ * < n and the indices distinct (HQC_EINVAL otherwise; HQC_ERANGE when
+ * key_id >= capacity).  Synchronous. */
+int hqc_keystore_put(hqc_keystore_t *ks, int param_id, uint32_t key_id,
+                     const uint32_t *y_host);
+/* The same for count consecutive slots from key_id0 (y_host: count * w). */
+int hqc_keystore_put_many(hqc_keystore_t *ks, int param_id, uint32_t key_id0,
+                          size_t count, const uint32_t *y_host);
+int hqc_keystore_destroy(hqc_keystore_t *ks);
+/* Items whose device key id was out of range since creation (they decrypt
+ * to zero bytes).  Synchronous. */
+int hqc_keystore_bad_ids(const hqc_keystore_t *ks, uint64_t *out);
+
+/* hqc_decrypt_batch with y taken from the keystore: item i uses slot
+ * key_ids[i] (device array of count uint32) of params->param_id. */
+int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks,
+                            const uint64_t *u, const uint64_t *v,
+                            const uint32_t *key_ids, uint8_t *m_out, size_t count);
+
+/* Static text for an HQC_* code. */
+const char *hqc_strerror(int code);
+/* hipError_t of the last HQC_EHIP on this thread (0 if none). */
+int hqc_last_hip_error(void);
+/* Number of persistent workgroups the library would launch for param_id
+ * (0 = mixed) on the current device; HQC_EINVAL / HQC_EHIP on error. */
+int hqc_default_grid(int param_id);
+/* Releases cached graphs.  Keystores stay valid. */
+void hqc_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HQC_GPU_H */
