@@ -1,0 +1,56 @@
+"""Build steps for the in-tree native libraries.
+
+libhqc_gpu.so   hipcc, gfx950: kernels + C ABI (include/hqc_gpu.h)
+libhqc_synth.so gcc: seeded input generator
+"""
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+GPU_SO = os.path.join(HERE, "libhqc_gpu.so")
+GPU_SOURCES = [os.path.join(CSRC, "hqc_kernels.hip"), os.path.join(CSRC, "hqc_capi.cpp")]
+GPU_HEADERS = [os.path.join(CSRC, "hqc_internal.h"), os.path.join(ROOT, "include", "hqc_gpu.h")]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no packed-FP32 instructions in any generated code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-command-line-argument",
+]
+
+
+def hipcc():
+    p = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    return p
+
+
+def build_gpu(verbose=False):
+    """Compile the HIP library for gfx950 (cross-compiles without a GPU)."""
+    tmp = GPU_SO + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                     "-o", tmp] + GPU_SOURCES
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, stderr=None if verbose else subprocess.DEVNULL)
+    os.replace(tmp, GPU_SO)
+    return GPU_SO
+
+
+def gpu_stale():
+    if not os.path.exists(GPU_SO):
+        return True
+    t = os.path.getmtime(GPU_SO)
+    return any(os.path.getmtime(s) > t for s in GPU_SOURCES + GPU_HEADERS)
+
+
+def build_synth():
+    from . import synth
+    synth.build()
+
+
+def build_all(verbose=False):
+    build_synth()
+    build_gpu(verbose=verbose)

@@ -1,0 +1,454 @@
+// hqc_capi.cpp -- the C ABI of include/hqc_gpu.h: argument validation,
+// launch configuration, hipGraph cache, per-item baseline mode, keystore.
+#include "hqc_gpu.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "hqc_internal.h"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return HQC_EHIP;
+}
+
+int pid_bit(int pid) { return pid == 1 ? 1 : pid == 3 ? 2 : pid == 5 ? 4 : 0; }
+
+// Device memory check: [p, p + bytes) must lie inside one device allocation.
+// This keeps a wrong count or a host pointer from reaching a kernel.
+bool in_device_allocation(const void *p, size_t bytes) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return false;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const char *b = (const char *)base, *q = (const char *)p;
+  return q >= b && (size_t)(q - b) <= size && bytes <= size - (size_t)(q - b);
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+struct Grid {
+  std::mutex mu;
+  std::map<std::tuple<int, int, unsigned>, int> cache;  // (device, op, mask) -> grid
+};
+Grid g_grid;
+
+int default_grid(int op, unsigned mask, int *out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lk(g_grid.mu);
+  auto key = std::make_tuple(dev, op, mask);
+  auto it = g_grid.cache.find(key);
+  if (it != g_grid.cache.end()) {
+    *out = it->second;
+    return HQC_OK;
+  }
+  int cus = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hqc::kernel_ptr(op, mask), 64,
+                                                   hqc::lds_bytes_for(mask));
+  if (e != hipSuccess) return hip_fail(e);
+  if (per_cu < 1) per_cu = 1;
+  *out = cus * per_cu;
+  g_grid.cache[key] = *out;
+  return HQC_OK;
+}
+
+// hipGraph cache: one instantiated graph per distinct launch.
+struct GraphKey {
+  int op;
+  unsigned mask;
+  int grid;
+  int device;
+  std::vector<unsigned char> args;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(op, mask, grid, device, args) < std::tie(o.op, o.mask, o.grid, o.device, o.args);
+  }
+};
+struct GraphCache {
+  std::mutex mu;
+  std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> entries;
+};
+GraphCache g_graphs;
+const size_t kMaxGraphs = 64;
+
+void clear_graphs_locked() {
+  for (auto &kv : g_graphs.entries) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  g_graphs.entries.clear();
+}
+
+int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  GraphKey key{op, mask, grid, dev, std::vector<unsigned char>(sizeof a)};
+  std::memcpy(key.args.data(), &a, sizeof a);
+  std::lock_guard<std::mutex> lk(g_graphs.mu);
+  auto it = g_graphs.entries.find(key);
+  if (it == g_graphs.entries.end()) {
+    if (g_graphs.entries.size() >= kMaxGraphs) clear_graphs_locked();
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphCreate(&graph, 0);
+    if (e != hipSuccess) return hip_fail(e);
+    hqc::KArgs copy = a;
+    void *params[] = {&copy};
+    hipKernelNodeParams np;
+    std::memset(&np, 0, sizeof np);
+    np.func = const_cast<void *>(hqc::kernel_ptr(op, mask));
+    np.gridDim = dim3((unsigned)grid);
+    np.blockDim = dim3(64);
+    np.sharedMemBytes = (unsigned)hqc::lds_bytes_for(mask);
+    np.kernelParams = params;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &np);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e);
+    }
+    it = g_graphs.entries.emplace(key, std::make_pair(graph, exec)).first;
+  }
+  e = hipGraphLaunch(it->second.second, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
+int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
+  hipStream_t st = (hipStream_t)p->stream;
+  if (a.total == 0) return HQC_OK;
+  int grid = p->grid;
+  if (grid <= 0) {
+    int rc = default_grid(op, mask, &grid);
+    if (rc) return rc;
+  }
+  if ((uint32_t)grid > a.total) grid = (int)a.total;
+  if (p->flags & HQC_F_PER_ITEM_LAUNCH) {
+    // Baseline mode: the same kernel, one launch per item (count = 1).
+    for (uint32_t s = 0; s < a.nseg; ++s) {
+      const hqc::SegDev &sg = a.seg[s];
+      hqc::SetInfo si;
+      hqc::set_info(sg.pid, &si);
+      for (uint32_t i = 0; i < sg.count; ++i) {
+        hqc::KArgs one;
+        std::memset(&one, 0, sizeof one);
+        one.nseg = 1;
+        one.total = 1;
+        hqc::SegDev &o = one.seg[0];
+        o = sg;
+        o.first = 0;
+        o.count = 1;
+        const size_t in_words = op == hqc::OP_DECODE ? (size_t)si.v_words : (size_t)si.u_words;
+        o.u = sg.u + (size_t)i * in_words;
+        if (sg.v) o.v = sg.v + (size_t)i * si.v_words;
+        if (sg.y) o.y = sg.y + (size_t)i * si.w;
+        if (sg.key_ids) o.key_ids = sg.key_ids + i;
+        o.m = sg.m + (size_t)i * si.k;
+        hipError_t e = hqc::launch(op, (unsigned)pid_bit(sg.pid), one, 1, st);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+    }
+    return HQC_OK;
+  }
+  if (p->flags & HQC_F_GRAPH) return launch_graph(op, mask, a, grid, st);
+  hipError_t e = hqc::launch(op, mask, a, grid, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
+int check_params(const hqc_params_t *p) {
+  if (!p || p->reserved != 0) return HQC_EINVAL;
+  if (p->flags & ~(HQC_F_PER_ITEM_LAUNCH | HQC_F_GRAPH)) return HQC_EINVAL;
+  if ((p->flags & HQC_F_PER_ITEM_LAUNCH) && (p->flags & HQC_F_GRAPH)) return HQC_EINVAL;
+  if (p->grid < 0) return HQC_EINVAL;
+  return HQC_OK;
+}
+
+// Validates one segment and fills its device descriptor.
+int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::SegDev *o) {
+  hqc::SetInfo si;
+  if (!hqc::set_info(s.param_id, &si) || s.reserved != 0) return HQC_EINVAL;
+  if (s.count > HQC_MAX_COUNT) return HQC_ERANGE;
+  std::memset(o, 0, sizeof *o);
+  o->pid = s.param_id;
+  o->count = (uint32_t)s.count;
+  if (s.count == 0) return HQC_OK;
+  const size_t c = s.count;
+  if (!s.u || !s.m_out || !aligned(s.u, 8)) return HQC_EINVAL;
+  if (op == hqc::OP_DECODE) {
+    if (!in_device_allocation(s.u, c * si.v_words * 8)) return HQC_EINVAL;
+  } else {
+    if (!s.v || !aligned(s.v, 8)) return HQC_EINVAL;
+    if (!in_device_allocation(s.u, c * si.u_words * 8)) return HQC_EINVAL;
+    if (!in_device_allocation(s.v, c * si.v_words * 8)) return HQC_EINVAL;
+    if (op == hqc::OP_DECRYPT) {
+      if (!s.y || !aligned(s.y, 4) || !in_device_allocation(s.y, c * si.w * 4)) return HQC_EINVAL;
+    } else {
+      if (!key_ids || !aligned(key_ids, 4) || !in_device_allocation(key_ids, c * 4))
+        return HQC_EINVAL;
+    }
+  }
+  if (!in_device_allocation(s.m_out, c * si.k)) return HQC_EINVAL;
+  o->u = s.u;
+  o->v = s.v;
+  o->y = s.y;
+  o->key_ids = key_ids;
+  o->m = s.m_out;
+  return HQC_OK;
+}
+
+int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
+                 const hqc_keystore_t *ks, const uint32_t *key_ids);
+
+}  // namespace
+
+struct hqc_keystore {
+  size_t cap[3];
+  uint32_t *y[3];
+  unsigned long long *bad;
+  int device;
+};
+
+namespace {
+
+int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
+                 const hqc_keystore_t *ks, const uint32_t *key_ids) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!segs || nseg < 1 || nseg > 3) return HQC_EINVAL;
+  hqc::KArgs a;
+  std::memset(&a, 0, sizeof a);
+  unsigned mask = 0, seen = 0;
+  uint64_t total = 0;
+  for (int i = 0; i < nseg; ++i) {
+    if (seen & (unsigned)pid_bit(segs[i].param_id)) return HQC_EINVAL;  // one per set
+    seen |= (unsigned)pid_bit(segs[i].param_id);
+    hqc::SegDev sd;
+    rc = fill_segment(op, segs[i], key_ids, &sd);
+    if (rc) return rc;
+    if (sd.count == 0) continue;
+    if (op == hqc::OP_KEYED) {
+      int slot = segs[i].param_id == 1 ? 0 : segs[i].param_id == 3 ? 1 : 2;
+      sd.ks_y = ks->y[slot];
+      sd.ks_cap = (uint32_t)ks->cap[slot];
+      sd.ks_bad = ks->bad;
+    }
+    mask |= (unsigned)pid_bit(segs[i].param_id);
+    sd.first = (uint32_t)total;
+    total += sd.count;
+    a.seg[a.nseg++] = sd;
+  }
+  if (total > HQC_MAX_COUNT) return HQC_ERANGE;
+  a.total = (uint32_t)total;
+  if (a.total == 0) return HQC_OK;
+  return run(op, p, a, mask);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hqc_sizes(int param_id, hqc_sizes_t *out) {
+  hqc::SetInfo si;
+  if (!out || !hqc::set_info(param_id, &si)) return HQC_EINVAL;
+  out->param_id = param_id;
+  out->n = si.n;
+  out->n1 = si.n1;
+  out->k = si.k;
+  out->delta = si.delta;
+  out->n2 = si.n2;
+  out->mult = si.mult;
+  out->w = si.w;
+  // encryption-side weights (Table I), reported for completeness
+  out->wr = out->we = param_id == 1 ? 75 : param_id == 3 ? 114 : 149;
+  out->u_words = si.u_words;
+  out->v_words = si.v_words;
+  return HQC_OK;
+}
+
+int hqc_decrypt_batch(const hqc_params_t *params, const uint64_t *u, const uint64_t *v,
+                      const uint32_t *y, uint8_t *m_out, size_t count) {
+  if (!params) return HQC_EINVAL;
+  hqc_segment_t s;
+  std::memset(&s, 0, sizeof s);
+  s.param_id = params->param_id;
+  s.count = count;
+  s.u = u;
+  s.v = v;
+  s.y = y;
+  s.m_out = m_out;
+  return run_segments(hqc::OP_DECRYPT, params, &s, 1, nullptr, nullptr);
+}
+
+int hqc_decode_batch(const hqc_params_t *params, const uint64_t *r, uint8_t *m_out,
+                     size_t count) {
+  if (!params) return HQC_EINVAL;
+  hqc_segment_t s;
+  std::memset(&s, 0, sizeof s);
+  s.param_id = params->param_id;
+  s.count = count;
+  s.u = r;
+  s.m_out = m_out;
+  return run_segments(hqc::OP_DECODE, params, &s, 1, nullptr, nullptr);
+}
+
+int hqc_decrypt_mixed(const hqc_params_t *params, const hqc_segment_t *segs, int nseg) {
+  return run_segments(hqc::OP_DECRYPT, params, segs, nseg, nullptr, nullptr);
+}
+
+int hqc_decode_mixed(const hqc_params_t *params, const hqc_segment_t *segs, int nseg) {
+  if (segs)
+    for (int i = 0; i < nseg && i < 3; ++i)
+      if (segs[i].v || segs[i].y) return HQC_EINVAL;
+  return run_segments(hqc::OP_DECODE, params, segs, nseg, nullptr, nullptr);
+}
+
+int hqc_keystore_create(hqc_keystore_t **ks, const size_t cap[3]) {
+  if (!ks || !cap) return HQC_EINVAL;
+  *ks = nullptr;
+  for (int i = 0; i < 3; ++i)
+    if (cap[i] > 0xFFFFFFFFull) return HQC_ERANGE;
+  hqc_keystore *k = new (std::nothrow) hqc_keystore;
+  if (!k) return HQC_ENOMEM;
+  std::memset(k, 0, sizeof *k);
+  hipError_t e = hipGetDevice(&k->device);
+  if (e != hipSuccess) {
+    delete k;
+    return hip_fail(e);
+  }
+  const int pids[3] = {1, 3, 5};
+  for (int i = 0; i < 3; ++i) {
+    hqc::SetInfo si;
+    hqc::set_info(pids[i], &si);
+    k->cap[i] = cap[i];
+    size_t bytes = (cap[i] ? cap[i] : 1) * (size_t)si.w * 4;
+    e = hipMalloc(&k->y[i], bytes);
+    if (e == hipSuccess) e = hipMemset(k->y[i], 0, bytes);
+    if (e != hipSuccess) {
+      hqc_keystore_destroy(k);
+      return e == hipErrorOutOfMemory ? HQC_ENOMEM : hip_fail(e);
+    }
+  }
+  e = hipMalloc(&k->bad, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(k->bad, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    hqc_keystore_destroy(k);
+    return hip_fail(e);
+  }
+  *ks = k;
+  return HQC_OK;
+}
+
+int hqc_keystore_put_many(hqc_keystore_t *ks, int param_id, uint32_t key_id0, size_t count,
+                          const uint32_t *y_host) {
+  hqc::SetInfo si;
+  if (!ks || !hqc::set_info(param_id, &si)) return HQC_EINVAL;
+  if (count == 0) return HQC_OK;
+  if (!y_host) return HQC_EINVAL;
+  const int slot = param_id == 1 ? 0 : param_id == 3 ? 1 : 2;
+  if ((size_t)key_id0 + count > ks->cap[slot]) return HQC_ERANGE;
+  std::vector<uint8_t> seen((size_t)si.n);
+  for (size_t i = 0; i < count; ++i) {
+    const uint32_t *yy = y_host + i * si.w;
+    for (int j = 0; j < si.w; ++j) {
+      if (yy[j] >= (uint32_t)si.n || seen[yy[j]]) {
+        for (int t = 0; t < j; ++t) seen[yy[t]] = 0;
+        return HQC_EINVAL;
+      }
+      seen[yy[j]] = 1;
+    }
+    for (int j = 0; j < si.w; ++j) seen[yy[j]] = 0;
+  }
+  hipError_t e = hipMemcpy(ks->y[slot] + (size_t)key_id0 * si.w, y_host, count * si.w * 4,
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
+int hqc_keystore_put(hqc_keystore_t *ks, int param_id, uint32_t key_id, const uint32_t *y_host) {
+  return hqc_keystore_put_many(ks, param_id, key_id, 1, y_host);
+}
+
+int hqc_keystore_destroy(hqc_keystore_t *ks) {
+  if (!ks) return HQC_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (ks->y[i]) (void)hipFree(ks->y[i]);
+  if (ks->bad) (void)hipFree(ks->bad);
+  delete ks;
+  return HQC_OK;
+}
+
+int hqc_keystore_bad_ids(const hqc_keystore_t *ks, uint64_t *out) {
+  if (!ks || !out) return HQC_EINVAL;
+  unsigned long long v = 0;
+  hipError_t e = hipMemcpy(&v, ks->bad, sizeof v, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  *out = v;
+  return HQC_OK;
+}
+
+int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks,
+                            const uint64_t *u, const uint64_t *v, const uint32_t *key_ids,
+                            uint8_t *m_out, size_t count) {
+  if (!params || !ks) return HQC_EINVAL;
+  hqc_segment_t s;
+  std::memset(&s, 0, sizeof s);
+  s.param_id = params->param_id;
+  s.count = count;
+  s.u = u;
+  s.v = v;
+  s.m_out = m_out;
+  return run_segments(hqc::OP_KEYED, params, &s, 1, ks, key_ids);
+}
+
+const char *hqc_strerror(int code) {
+  switch (code) {
+    case HQC_OK: return "success";
+    case HQC_EINVAL: return "invalid argument (pointer, alignment, size, parameter id or flags)";
+    case HQC_ERANGE: return "count or key id out of range";
+    case HQC_EHIP: return "HIP runtime error (see hqc_last_hip_error)";
+    case HQC_ENOMEM: return "out of memory";
+    default: return "unknown error code";
+  }
+}
+
+int hqc_last_hip_error(void) { return g_last_hip; }
+
+int hqc_default_grid(int param_id) {
+  unsigned mask = param_id == 0 ? 7u : (unsigned)pid_bit(param_id);
+  if (!mask) return HQC_EINVAL;
+  int g = 0;
+  int rc = default_grid(hqc::OP_DECRYPT, mask, &g);
+  return rc ? rc : g;
+}
+
+void hqc_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_graphs.mu);
+  clear_graphs_locked();
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// hqc_internal.h -- interface between the C ABI (hqc_capi.cpp) and the
+// kernels (hqc_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hqc {
+
+enum Op : int { OP_DECRYPT = 0, OP_DECODE = 1, OP_KEYED = 2 };
+
+// One homogeneous run of items inside a launch.
+struct SegDev {
+  const uint64_t *u;        // decrypt: u; decode: received word r
+  const uint64_t *v;        // decrypt only
+  const uint32_t *y;        // decrypt only (count * w)
+  const uint32_t *key_ids;  // keyed only
+  const uint32_t *ks_y;     // keyed only: keystore slots of this parameter set
+  unsigned long long *ks_bad;  // keyed only: counter of out-of-range key ids
+  uint8_t *m;               // count * k
+  uint32_t ks_cap;          // keyed only: slots in ks_y
+  uint32_t count;
+  uint32_t first;           // index of the segment's first item in the launch
+  int32_t pid;              // 1, 3 or 5
+};
+
+struct KArgs {
+  SegDev seg[3];
+  uint32_t nseg;
+  uint32_t total;
+};
+
+// Per-parameter sizes as the kernels see them.
+struct SetInfo {
+  int n, n1, n2, k, delta, w, mult;
+  int u_words, v_words;
+  size_t lds_bytes;  // dynamic LDS one workgroup needs for this set
+};
+
+bool set_info(int pid, SetInfo *out);
+// mask: bit 0 = HQC-1, bit 1 = HQC-3, bit 2 = HQC-5 present in the launch.
+const void *kernel_ptr(int op, unsigned mask);
+size_t lds_bytes_for(unsigned mask);
+hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream);
+
+}  // namespace hqc

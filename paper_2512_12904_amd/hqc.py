@@ -1,0 +1,265 @@
+"""Python binding of libhqc_gpu.so (include/hqc_gpu.h).
+
+Argument marshalling only: torch device tensors in, their device pointers
+and the current HIP stream out to the C ABI.  Every step of decryption runs
+in the library's kernels; if the library cannot be loaded these functions
+raise -- there is no fallback.
+
+Tensor layouts (per item, row-major, on the GPU):
+  u  int64 [count, u_words]   bit t of u is bit t % 64 of word t // 64
+  v  int64 [count, v_words]   (or r for decode)
+  y  int32 [count, w]         support indices of the secret key
+  m  uint8 [count, k]
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libhqc_gpu.so")
+
+HQC_OK, HQC_EINVAL, HQC_ERANGE, HQC_EHIP, HQC_ENOMEM = 0, -1, -2, -3, -4
+F_PER_ITEM_LAUNCH = 0x1
+F_GRAPH = 0x2
+
+# every function declared in include/hqc_gpu.h
+EXPORTS = (
+    "hqc_sizes", "hqc_decrypt_batch", "hqc_decode_batch", "hqc_decrypt_mixed",
+    "hqc_decode_mixed", "hqc_keystore_create", "hqc_keystore_put", "hqc_keystore_put_many",
+    "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
+    "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown",
+)
+
+
+class HqcError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        msg = "%s failed: %s (%d)" % (what, strerror(code), code)
+        if code == HQC_EHIP:
+            msg += ", hipError %d" % lib().hqc_last_hip_error()
+        super().__init__(msg)
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in (
+        "param_id", "n", "n1", "k", "delta", "n2", "mult", "w", "wr", "we", "u_words",
+        "v_words")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("param_id", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("param_id", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("count", ctypes.c_size_t), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("m_out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError("libhqc_gpu.so is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(SO_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.hqc_sizes.argtypes = [ctypes.c_int, ctypes.POINTER(Sizes)]
+        L.hqc_decrypt_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, sz]
+        L.hqc_decode_batch.argtypes = [ctypes.POINTER(Params), vp, vp, sz]
+        L.hqc_decrypt_mixed.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Segment), ctypes.c_int]
+        L.hqc_decode_mixed.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Segment), ctypes.c_int]
+        L.hqc_keystore_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.hqc_keystore_put.argtypes = [vp, ctypes.c_int, ctypes.c_uint32, vp]
+        L.hqc_keystore_put_many.argtypes = [vp, ctypes.c_int, ctypes.c_uint32, sz, vp]
+        L.hqc_keystore_destroy.argtypes = [vp]
+        L.hqc_keystore_bad_ids.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.hqc_decrypt_batch_keyed.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, sz]
+        L.hqc_strerror.restype = ctypes.c_char_p
+        L.hqc_strerror.argtypes = [ctypes.c_int]
+        L.hqc_last_hip_error.argtypes = []
+        L.hqc_default_grid.argtypes = [ctypes.c_int]
+        L.hqc_shutdown.restype = None
+        L.hqc_shutdown.argtypes = []
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().hqc_strerror(code).decode()
+
+
+def _check(rc, what):
+    if rc != HQC_OK:
+        raise HqcError(rc, what)
+
+
+def sizes(pid):
+    s = Sizes()
+    _check(lib().hqc_sizes(pid, ctypes.byref(s)), "hqc_sizes")
+    return {f: getattr(s, f) for f, _ in Sizes._fields_}
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _params(pid, flags, grid, stream):
+    return Params(pid, flags, _stream(stream), grid, 0)
+
+
+def _dev(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def _out(out, count, k, device):
+    if out is None:
+        out = torch.empty((count, k), dtype=torch.uint8, device=device)
+    return out
+
+
+def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None):
+    """m[i] = HQC.PKE.Decrypt(y[i], (u[i], v[i])) for every row (Alg. 2)."""
+    s = sizes(pid)
+    count = u.shape[0]
+    out = _out(out, count, s["k"], u.device)
+    p = _params(pid, flags, grid, stream)
+    rc = lib().hqc_decrypt_batch(
+        ctypes.byref(p), _dev(u, torch.int64, "u", (count, s["u_words"])),
+        _dev(v, torch.int64, "v", (count, s["v_words"])),
+        _dev(y, torch.int32, "y", (count, s["w"])),
+        _dev(out, torch.uint8, "out", (count, s["k"])), count)
+    _check(rc, "hqc_decrypt_batch")
+    return out
+
+
+def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None):
+    """m[i] = C.Decode(r[i]) (the concatenated decoder alone)."""
+    s = sizes(pid)
+    count = r.shape[0]
+    out = _out(out, count, s["k"], r.device)
+    p = _params(pid, flags, grid, stream)
+    rc = lib().hqc_decode_batch(ctypes.byref(p), _dev(r, torch.int64, "r", (count, s["v_words"])),
+                                _dev(out, torch.uint8, "out", (count, s["k"])), count)
+    _check(rc, "hqc_decode_batch")
+    return out
+
+
+def _segments(items, decode):
+    segs = (Segment * len(items))()
+    outs = []
+    for i, it in enumerate(items):
+        pid = it["pid"]
+        s = sizes(pid)
+        u = it["r"] if decode else it["u"]
+        count = u.shape[0]
+        out = _out(it.get("out"), count, s["k"], u.device)
+        outs.append(out)
+        segs[i].param_id = pid
+        segs[i].count = count
+        segs[i].u = _dev(u, torch.int64, "u/r", (count, s["v_words"] if decode else s["u_words"]))
+        if not decode:
+            segs[i].v = _dev(it["v"], torch.int64, "v", (count, s["v_words"]))
+            segs[i].y = _dev(it["y"], torch.int32, "y", (count, s["w"]))
+        segs[i].m_out = _dev(out, torch.uint8, "out", (count, s["k"]))
+    return segs, outs
+
+
+def decrypt_mixed(items, flags=0, grid=0, stream=None):
+    """One launch over several parameter sets.  items: list of dicts with
+    pid, u, v, y (and optionally out); returns the list of outputs."""
+    segs, outs = _segments(items, decode=False)
+    p = _params(0, flags, grid, stream)
+    _check(lib().hqc_decrypt_mixed(ctypes.byref(p), segs, len(items)), "hqc_decrypt_mixed")
+    return outs
+
+
+def decode_mixed(items, flags=0, grid=0, stream=None):
+    """items: list of dicts with pid, r (and optionally out)."""
+    segs, outs = _segments(items, decode=True)
+    p = _params(0, flags, grid, stream)
+    _check(lib().hqc_decode_mixed(ctypes.byref(p), segs, len(items)), "hqc_decode_mixed")
+    return outs
+
+
+class KeyStore:
+    """Device-resident secret keys y, capacity per parameter set."""
+
+    def __init__(self, cap1, cap3, cap5):
+        self._h = ctypes.c_void_p()
+        cap = (ctypes.c_size_t * 3)(cap1, cap3, cap5)
+        _check(lib().hqc_keystore_create(ctypes.byref(self._h), cap), "hqc_keystore_create")
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("keystore destroyed")
+        return self._h
+
+    def put(self, pid, key_id0, y_host):
+        """y_host: numpy uint32 [count, w] (host memory)."""
+        import numpy as np
+        y_host = np.ascontiguousarray(y_host, dtype=np.uint32)
+        if y_host.ndim == 1:
+            y_host = y_host[None, :]
+        rc = lib().hqc_keystore_put_many(self.handle, pid, key_id0, y_host.shape[0],
+                                         y_host.ctypes.data_as(ctypes.c_void_p))
+        _check(rc, "hqc_keystore_put_many")
+
+    def bad_ids(self):
+        v = ctypes.c_uint64()
+        _check(lib().hqc_keystore_bad_ids(self.handle, ctypes.byref(v)), "hqc_keystore_bad_ids")
+        return v.value
+
+    def close(self):
+        if self._h:
+            lib().hqc_keystore_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, stream=None):
+    """decrypt_batch with y[i] = slot key_ids[i] of the keystore."""
+    s = sizes(pid)
+    count = u.shape[0]
+    out = _out(out, count, s["k"], u.device)
+    p = _params(pid, flags, grid, stream)
+    rc = lib().hqc_decrypt_batch_keyed(
+        ctypes.byref(p), ks.handle, _dev(u, torch.int64, "u", (count, s["u_words"])),
+        _dev(v, torch.int64, "v", (count, s["v_words"])),
+        _dev(key_ids, torch.int32, "key_ids", (count,)),
+        _dev(out, torch.uint8, "out", (count, s["k"])), count)
+    _check(rc, "hqc_decrypt_batch_keyed")
+    return out
+
+
+def default_grid(pid):
+    g = lib().hqc_default_grid(pid)
+    if g < 0:
+        raise HqcError(g, "hqc_default_grid")
+    return g
+
+
+def shutdown():
+    lib().hqc_shutdown()

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/hqc_gpu.h, reports the Table I sizes, and rejects bad
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gpu_lib():
+    from paper_2512_12904_amd import build, hqc
+    if build.gpu_stale():
+        build.build_gpu()
+    return hqc
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hqc_gpu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hqc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree(gpu_lib):
+    assert declared_functions() == sorted(gpu_lib.EXPORTS)
+
+
+def test_every_declared_symbol_exported(gpu_lib):
+    L = ctypes.CDLL(gpu_lib.SO_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_sizes_match_table_i(gpu_lib, orc):
+    for pid in (1, 3, 5):
+        s = gpu_lib.sizes(pid)
+        p = orc.param(pid)
+        for a, b in (("n", "n"), ("n1", "n1"), ("k", "k"), ("delta", "delta"), ("n2", "n2"),
+                     ("mult", "mult"), ("w", "w"), ("wr", "wr"), ("we", "we"),
+                     ("u_words", "nwords"), ("v_words", "vwords")):
+            assert s[a] == p[b], (pid, a)
+    with pytest.raises(gpu_lib.HqcError):
+        gpu_lib.sizes(2)
+
+
+def test_strerror(gpu_lib):
+    for code in (0, -1, -2, -3, -4):
+        assert gpu_lib.strerror(code)
+    assert "unknown" in gpu_lib.strerror(7)
+
+
+def test_invalid_arguments_rejected_before_launch(gpu_lib):
+    L = gpu_lib.lib()
+    P = gpu_lib.Params
+    vp = ctypes.c_void_p
+    # NULL params
+    assert L.hqc_decrypt_batch(None, vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    # bad parameter id
+    p = P(2, 0, None, 0, 0)
+    assert L.hqc_decrypt_batch(ctypes.byref(p), vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    # unknown flag, conflicting flags, reserved field, negative grid
+    for bad in (P(1, 0x100, None, 0, 0), P(1, 3, None, 0, 0), P(1, 0, None, 0, 1),
+                P(1, 0, None, -1, 0)):
+        assert L.hqc_decrypt_batch(ctypes.byref(bad), vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    p = P(1, 0, None, 0, 0)
+    # NULL buffers with count > 0
+    assert L.hqc_decrypt_batch(ctypes.byref(p), None, vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    assert L.hqc_decode_batch(ctypes.byref(p), None, vp(8), 1) == gpu_lib.HQC_EINVAL
+    # misaligned u
+    assert L.hqc_decrypt_batch(ctypes.byref(p), vp(12), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    # oversize count
+    assert L.hqc_decode_batch(ctypes.byref(p), vp(8), vp(8), 1 << 40) == gpu_lib.HQC_ERANGE
+    # count == 0 is a no-op, whatever the pointers
+    assert L.hqc_decrypt_batch(ctypes.byref(p), None, None, None, None, 0) == gpu_lib.HQC_OK
+    assert L.hqc_decode_batch(ctypes.byref(p), None, None, 0) == gpu_lib.HQC_OK
+    # mixed: too many segments / repeated set
+    segs = (gpu_lib.Segment * 4)()
+    assert L.hqc_decode_mixed(ctypes.byref(p), segs, 4) == gpu_lib.HQC_EINVAL
+    segs2 = (gpu_lib.Segment * 2)()
+    segs2[0].param_id = segs2[1].param_id = 1
+    assert L.hqc_decode_mixed(ctypes.byref(p), segs2, 2) == gpu_lib.HQC_EINVAL
+    # keystore argument checks
+    assert L.hqc_keystore_create(None, None) == gpu_lib.HQC_EINVAL
+    assert L.hqc_keystore_destroy(None) == gpu_lib.HQC_EINVAL
+    assert L.hqc_decrypt_batch_keyed(ctypes.byref(p), None, vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+
+
+def test_host_pointer_rejected_without_gpu(gpu_lib):
+    # a host buffer is not device memory: refused before any launch
+    import numpy as np
+    L = gpu_lib.lib()
+    p = gpu_lib.Params(1, 0, None, 0, 0)
+    buf = np.zeros(4096, np.uint64)
+    ptr = ctypes.c_void_p(buf.ctypes.data)
+    assert L.hqc_decode_batch(ctypes.byref(p), ptr, ptr, 1) == gpu_lib.HQC_EINVAL

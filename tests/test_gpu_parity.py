@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle and the
+ground-truth messages, bit-exact (integer work: the tolerance is zero)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12904_amd import synth
+from tests import datasets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hqc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc as h
+    h.lib()
+    return h
+
+
+def dev(a):
+    import torch
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    elif a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_hqc1_batch64(hqc, shared):
+    say("case: HQC-1 x64 shared_key=%s" % shared)
+    d = datasets.pke(1, 64, 0x1, shared_key=shared)
+    got = host(hqc.decrypt_batch(1, dev(d["u"]), dev(d["v"]), dev(d["y"])))
+    assert (got == d["m"]).all()
+    ref = oracle.decrypt_batch(1, d["y"], d["u"], d["v"])
+    assert (got == ref).all()
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+@pytest.mark.parametrize("count,grid", [(1, 0), (7, 0), (130, 0), (130, 7), (257, 64)])
+def test_ragged_counts_and_persistent_grid(hqc, pid, count, grid):
+    say("case: pid=%d count=%d grid=%d" % (pid, count, grid))
+    d = datasets.pke(pid, count, 0x100 + pid)
+    got = host(hqc.decrypt_batch(pid, dev(d["u"]), dev(d["v"]), dev(d["y"]), grid=grid))
+    assert (got == d["m"]).all()
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_beyond_radius_matches_oracle(hqc, pid):
+    # uniform u, v and arbitrary y (indices >= n, repeats, 0 and n-1): no valid
+    # message exists, the output is fixed only by the decoder conventions
+    say("case: beyond radius pid=%d" % pid)
+    p = datasets.sizes(pid)
+    cnt = 96
+    u = synth.words(0x51 + pid, (cnt, p["nwords"]))
+    v = synth.words(0x61 + pid, (cnt, p["vwords"]))
+    rng = np.random.default_rng(pid)
+    y = rng.integers(0, 2 ** 32, (cnt, p["w"]), dtype=np.uint64).astype(np.uint32)
+    y[0, :] = 0
+    y[1, :2] = [0, p["n"] - 1]
+    y[2, :] = p["n"] - 1
+    y[3, 1] = y[3, 0]
+    y[4:40] %= p["n"]
+    got = host(hqc.decrypt_batch(pid, dev(u), dev(v), dev(y)))
+    ref = oracle.decrypt_batch(pid, y, u, v)
+    assert (got == ref).all()
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_u_zero_and_high_bits_ignored(hqc, pid):
+    say("case: u edge pid=%d" % pid)
+    d = datasets.pke(pid, 24, 0x200 + pid)
+    p = datasets.sizes(pid)
+    u = d["u"].copy()
+    u[:, -1] |= np.uint64(0xFFFFFFFFFFFFFFFF) << np.uint64(p["n"] % 64)  # bits >= n set
+    got = host(hqc.decrypt_batch(pid, dev(u), dev(d["v"]), dev(d["y"])))
+    assert (got == d["m"]).all()
+    # u = 0: decryption is C.Decode(v)
+    z = np.zeros_like(d["u"])
+    cw = np.stack([oracle.code_encode(pid, mm) for mm in d["m"]])
+    got = host(hqc.decrypt_batch(pid, dev(z), dev(cw), dev(d["y"])))
+    assert (got == d["m"]).all()
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_decode_stress(hqc, pid):
+    say("case: decode stress pid=%d" % pid)
+    d = datasets.stress(pid, 300, 0x4)
+    got = host(hqc.decode_batch(pid, dev(d["r"])))
+    assert (got == d["m"]).all()
+    # decode == decrypt with u = 0
+    p = datasets.sizes(pid)
+    z = np.zeros((300, p["nwords"]), np.uint64)
+    y = np.tile(np.arange(p["w"], dtype=np.uint32), (300, 1))
+    got2 = host(hqc.decrypt_batch(pid, dev(z), dev(d["r"]), dev(y)))
+    assert (got2 == got).all()
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_decode_random_words_match_oracle(hqc, pid):
+    say("case: decode random pid=%d" % pid)
+    p = datasets.sizes(pid)
+    r = synth.words(0x71 + pid, (64, p["vwords"]))
+    r[0] = 0
+    r[1] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    got = host(hqc.decode_batch(pid, dev(r)))
+    assert (got == oracle.decode_batch(pid, r)).all()
+
+
+def test_mixed_launch_equals_separate(hqc):
+    say("case: mixed decrypt + decode")
+    ds = {pid: datasets.pke(pid, 50 + pid, 0x300 + pid) for pid in (5, 1, 3)}
+    items = [{"pid": pid, "u": dev(d["u"]), "v": dev(d["v"]), "y": dev(d["y"])} for pid, d in ds.items()]
+    outs = hqc.decrypt_mixed(items, grid=37)
+    for (pid, d), o in zip(ds.items(), outs):
+        assert (host(o) == d["m"]).all()
+    st = {pid: datasets.stress(pid, 40, 0x44) for pid in (1, 3, 5)}
+    outs = hqc.decode_mixed([{"pid": pid, "r": dev(d["r"])} for pid, d in st.items()])
+    for (pid, d), o in zip(st.items(), outs):
+        assert (host(o) == d["m"]).all()
+
+
+def test_per_item_and_graph_modes(hqc):
+    say("case: per-item and graph launch modes")
+    d = datasets.pke(3, 33, 0x400)
+    u, v, y = dev(d["u"]), dev(d["v"]), dev(d["y"])
+    a = host(hqc.decrypt_batch(3, u, v, y, flags=hqc.F_PER_ITEM_LAUNCH))
+    assert (a == d["m"]).all()
+    for _ in range(3):
+        out = hqc.decrypt_batch(3, u, v, y, flags=hqc.F_GRAPH)
+        assert (host(out) == d["m"]).all()
+
+
+def test_keystore(hqc):
+    say("case: keystore")
+    import torch
+    d = datasets.pke(1, 40, 0x500)
+    ks = hqc.KeyStore(40, 1, 1)
+    ks.put(1, 0, d["y_keys"])
+    ids = torch.arange(40, dtype=torch.int32, device="cuda")
+    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids))
+    assert (got == d["m"]).all()
+    ids[5] = 1000  # out of range: zeros, counted
+    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids))
+    assert (got[5] == 0).all() and (np.delete(got, 5, 0) == np.delete(d["m"], 5, 0)).all()
+    assert ks.bad_ids() == 1
+    with pytest.raises(hqc.HqcError):
+        ks.put(1, 0, np.zeros(66, np.uint32))  # repeated index
+    with pytest.raises(hqc.HqcError):
+        ks.put(1, 40, d["y_keys"][:1])  # slot beyond capacity
+    ks.close()
+
+
+def test_bad_buffer_sizes_rejected(hqc):
+    import torch
+    say("case: size validation")
+    p = datasets.sizes(1)
+    r = torch.zeros((4, p["vwords"]), dtype=torch.int64, device="cuda")
+    out = torch.zeros((4, 16), dtype=torch.uint8, device="cuda")
+    L = hqc.lib()
+    import ctypes
+    prm = hqc.Params(1, 0, None, 0, 0)
+    # count larger than the allocation behind r: refused
+    rc = L.hqc_decode_batch(ctypes.byref(prm), ctypes.c_void_p(r.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr()), 1 << 20)
+    assert rc == hqc.HQC_EINVAL
