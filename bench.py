@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of batched HQC.PKE decryption on one MI355X.
+
+A step is one launch (a cached hipGraph holding the persistent fused kernel)
+that decrypts a whole batch of 65,536 HQC-1 ciphertexts already resident in
+HBM: product u*y, XOR with v, RM and RS decoding, k-byte messages written
+back.  Printed: one JSON line with the HQC-1 rate (`value`), the HQC-3 and
+HQC-5 rates, the one-launch-per-ciphertext baseline on the same kernel,
+per-launch latency percentiles, the roofline of the kernel and the CPU
+checker's rate on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes, one 32-bit integer op per lane per
+# clock at 2.4 GHz.
+PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+
+SETS = {  # Table I plus the derived sizes the op model needs
+    1: dict(n=17669, n1=46, n2=384, k=16, delta=15, w=66, wr=75, we=75),
+    3: dict(n=35851, n1=56, n2=640, k=24, delta=16, w=100, wr=114, we=114),
+    5: dict(n=57637, n1=90, n2=640, k=32, delta=29, w=131, wr=149, we=149),
+}
+
+
+def op_model(pid):
+    """Algorithmic integer operations of one decryption (what the method must
+    compute, not the dense work it avoids):
+      product  2 w W32      one funnel shift + one XOR per output dword per index
+      add v    W32
+      RM       n1 (128 mult + 7*128 + 2*128)   expand, butterflies, peak search
+      RS       6 ops per GF(2^8) product, products: syndromes 2d(n1-1),
+               BM 8d^2, evaluator 2d^2, Chien n1*2d, Forney n1*3d."""
+    s = SETS[pid]
+    mult = s["n2"] // 128
+    w32 = s["n1"] * s["n2"] // 32
+    d = s["delta"]
+    prod = 2 * s["w"] * w32
+    rm = s["n1"] * (128 * mult + 7 * 128 + 2 * 128)
+    gf = 2 * d * (s["n1"] - 1) + 8 * d * d + 2 * d * d + s["n1"] * 2 * d + s["n1"] * 3 * d
+    return prod + w32 + rm + 6 * gf
+
+
+def hbm_bytes(pid):
+    """u + v + y read, m written, per decryption."""
+    s = SETS[pid]
+    return 8 * ((s["n"] + 63) // 64) + 8 * (s["n1"] * s["n2"] // 64) + 4 * s["w"] + s["k"]
+
+
+def make_inputs(pid, count, seed, device):
+    """Synthetic ciphertexts: u and v uniform (an HQC ciphertext is
+    indistinguishable from uniform, and the kernel's work does not depend on
+    the values), y a seeded fixed-weight support per item."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    s = dict(SETS[pid])
+    _, _, y = synth.keys(seed, pid, s, count)
+    u = synth.words(seed ^ 0x75, (count, (s["n"] + 63) // 64))
+    v = synth.words(seed ^ 0x76, (count, s["n1"] * s["n2"] // 64))
+    t = lambda a, dt: torch.from_numpy(a.view(dt)).to(device)
+    return t(u, np.int64), t(v, np.int64), t(y, np.int32)
+
+
+def time_batched(hqc, pid, u, v, y, out, steps, warmup):
+    """Per-launch device times (ms) from HIP events on the launch stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
+def time_per_item(hqc, pid, u, v, y, out):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_PER_ITEM_LAUNCH)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
+
+
+def cpu_baseline(seconds_target=12.0):
+    """The CPU checker (oracle/) on the host cores: honest HQC-1 ciphertexts
+    made by the checker itself, decryption timed over a bounded sample."""
+    import numpy as np
+    import oracle
+    from paper_2512_12904_amd import synth
+    pid = 1
+    p = oracle.param(pid)
+    threads = oracle.default_threads()
+    # calibrate on a small batch, then size the sample to ~seconds_target of wall time
+    cnt0 = 512
+    h, x, y = synth.keys(0xC0, pid, p, cnt0)
+    s = oracle.keygen_batch(pid, h, x, y)
+    ko = np.arange(cnt0, dtype=np.int64)
+    m, r1, r2, e = synth.encryptions(0xC0, pid, p, cnt0, key_of=ko)
+    u, v = oracle.encrypt_batch(pid, h, s, m, r1, r2, e, key_of=ko)
+    t0 = time.perf_counter()
+    oracle.decrypt_batch(pid, y, u, v, nthreads=threads)
+    dt = max(time.perf_counter() - t0, 1e-4)
+    reps = max(1, int(seconds_target / dt))
+    reps = min(reps, 4096)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = oracle.decrypt_batch(pid, y, u, v, nthreads=threads)
+    wall = time.perf_counter() - t0
+    ok = bool((got == m).all())
+    return {"value": cnt0 * reps / wall, "unit": "decrypts/s", "cores": threads, "kind": "oracle",
+            "sample": "%d decryptions (%d HQC-1 ciphertexts x %d passes), honest ciphertexts "
+                      "from the checker, %d threads, %.1f s" % (cnt0 * reps, cnt0, reps, threads, wall),
+            "recovered_m": ok}, (pid, y, u, v, m)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--count", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU checker baseline")
+    ap.add_argument("--no-per-item", action="store_true", help="skip the per-launch baseline")
+    ap.add_argument("--sets", default="1,3,5")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the decryption batch has no cross-GPU step; "
+              "run with --gpus 1 (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import hqc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hqc.lib()
+    sets = [int(x) for x in args.sets.split(",")]
+    results = {}
+    for pid in sets:
+        u, v, y = make_inputs(pid, args.count, 0xBE00 + pid, dev)
+        out = torch.empty((args.count, SETS[pid]["k"]), dtype=torch.uint8, device=dev)
+        steps = args.steps if pid == 1 else max(5, args.steps // 2)
+        times, wall = time_batched(hqc, pid, u, v, y, out, steps, args.warmup)
+        r = {"ms_mean": sum(times) / len(times), "ms_p50": pct(times, 50), "ms_p99": pct(times, 99),
+             "steps": steps, "wall_s": wall}
+        r["decrypts_per_s"] = args.count * steps / wall
+        r["device_decrypts_per_s"] = args.count / (r["ms_mean"] / 1e3)
+        if not args.no_per_item:
+            r["per_item_s"] = time_per_item(hqc, pid, u, v, y, out)
+            r["per_item_decrypts_per_s"] = args.count / r["per_item_s"]
+            r["batched_over_per_item"] = r["decrypts_per_s"] / r["per_item_decrypts_per_s"]
+        ops = op_model(pid) * args.count
+        r["alu_frac"] = ops / (r["ms_mean"] / 1e3) / PEAK_INT_OPS
+        r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
+        results[pid] = r
+        del u, v, y, out
+        torch.cuda.empty_cache()
+
+    main_r = results[sets[0]]
+    pid0 = sets[0]
+    ops_launch = op_model(pid0) * args.count
+    achieved = ops_launch / (main_r["ms_mean"] / 1e3)
+    line = {
+        "metric": "HQC decrypts/sec at HQC-1/3/5 (batched vs per-ciphertext GPU path); p99 latency",
+        "value": main_r["decrypts_per_s"],
+        "unit": "decrypts/s",
+        "n_gpus": 1,
+        "steps": main_r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": main_r["wall_s"] * 1e3 / main_r["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "HQC-%d PKE decrypt, batch %d in one persistent hipGraph launch"
+                               % (pid0, args.count), "param_set": "HQC-%d" % pid0,
+                   "batch": args.count, "launch": "hipGraph, persistent grid"},
+        "p50_launch_ms": main_r["ms_p50"],
+        "p99_launch_ms": main_r["ms_p99"],
+        "per_set": {"HQC-%d" % k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                   for kk, vv in r.items()} for k, r in results.items()},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                     "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS, "traffic": None,
+                     "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
+                     "kernel_ms": main_r["ms_mean"]},
+    }
+    if not args.no_per_item:
+        line["per_item_decrypts_per_s"] = main_r["per_item_decrypts_per_s"]
+        line["batched_over_per_item"] = main_r["batched_over_per_item"]
+    if not args.no_cpu:
+        cb, sample = cpu_baseline()
+        # same run: the GPU decrypts the checker's sample and must agree bitwise
+        pid, y, u, v, m = sample
+        got = hqc.decrypt_batch(pid, torch.from_numpy(u.view(np.int64)).to(dev),
+                                torch.from_numpy(v.view(np.int64)).to(dev),
+                                torch.from_numpy(y.view(np.int32)).to(dev))
+        torch.cuda.synchronize()
+        cb["gpu_matches_sample"] = bool((got.cpu().numpy() == m).all())
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
