@@ -1,0 +1,82 @@
+"""Parity at the workload sizes, in the launch configuration bench.py times
+(default persistent grid, hipGraph launch):
+
+- 65,536 HQC-1 decryptions with independent keys, one launch;
+- 65,536 HQC-3 and 65,536 HQC-5 decryptions, one launch each;
+- 1,048,576 decoder stress words, 50/30/20 HQC-1/3/5, one mixed launch:
+  exactly delta RS symbol errors per word (duplicated RM codewords added to
+  delta blocks) plus noise within the RM radius elsewhere.
+
+Every output is compared with the message that was encrypted / encoded
+(ground truth); a sample is also decrypted by the CPU oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import datasets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hqc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc as h
+    h.lib()
+    return h
+
+
+def dev(a):
+    import torch
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    elif a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+@pytest.mark.parametrize("pid,master", [(1, 0x2), (3, 0x3), (5, 0x5)])
+def test_decrypt_65536_one_launch(hqc, pid, master):
+    import torch
+    count = 65536
+    print("case: full-size decrypt pid=%d count=%d" % (pid, count), flush=True)
+    d = datasets.pke(pid, count, master)
+    print("  generated", flush=True)
+    out = hqc.decrypt_batch(pid, dev(d["u"]), dev(d["v"]), dev(d["y"]), flags=hqc.F_GRAPH)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    bad = np.flatnonzero((got != d["m"]).any(1))
+    assert len(bad) == 0, "items differing from the encrypted message: %s" % bad[:10]
+    rng = np.random.default_rng(pid)
+    sample = np.sort(rng.choice(count, 512, replace=False))
+    ref = oracle.decrypt_batch(pid, d["y"][sample], d["u"][sample], d["v"][sample])
+    assert (got[sample] == ref).all()
+
+
+def test_decode_stress_1m_mixed_one_launch(hqc):
+    import torch
+    counts = {1: 524288, 3: 314573, 5: 209715}  # 50 / 30 / 20 of 1,048,576
+    assert sum(counts.values()) == 1 << 20
+    print("case: stress 1M mixed", flush=True)
+    data = {pid: datasets.stress(pid, c, 0x4) for pid, c in counts.items()}
+    print("  generated", flush=True)
+    items = [{"pid": pid, "r": dev(d["r"])} for pid, d in data.items()]
+    outs = hqc.decode_mixed(items, flags=hqc.F_GRAPH)
+    torch.cuda.synchronize()
+    for (pid, d), o in zip(data.items(), outs):
+        got = o.cpu().numpy()
+        bad = np.flatnonzero((got != d["m"]).any(1))
+        assert len(bad) == 0, "pid %d: %d words wrong, first %s" % (pid, len(bad), bad[:10])
+    # the same words in separate homogeneous launches give the same bytes
+    for it, o in zip(items, outs):
+        sep = hqc.decode_batch(it["pid"], it["r"][:4096])
+        torch.cuda.synchronize()
+        assert torch.equal(sep, o[:4096])
+    # oracle on a sample of each set
+    for pid, d in data.items():
+        ref = oracle.decode_batch(pid, d["r"][:256])
+        assert (outs[[1, 3, 5].index(pid)][:256].cpu().numpy() == ref).all()
