@@ -89,7 +89,8 @@ typedef struct hqc_params {
   uint32_t flags;   /* HQC_F_* */
   void *stream;     /* hipStream_t, or NULL for the null stream */
   int32_t grid;     /* persistent workgroups; 0 = chosen by the library */
-  int32_t reserved; /* must be 0 */
+  int32_t tile;     /* items per workgroup tile, 1..64; 0 = chosen by the library.
+                       Results never depend on grid or tile. */
 } hqc_params_t;
 
 /* One homogeneous part of a mixed-parameter batch (host struct). */

@@ -138,14 +138,37 @@ int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream
   return HQC_OK;
 }
 
+// Splits the segments into tiles of `tile` items; returns the tile count.
+uint32_t assign_tiles(hqc::KArgs &a, uint32_t tile) {
+  uint32_t t = 0;
+  for (uint32_t s = 0; s < a.nseg; ++s) {
+    a.seg[s].first = t;
+    t += (a.seg[s].count + tile - 1) / tile;
+  }
+  a.tile = tile;
+  a.total = t;
+  return t;
+}
+
 int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
   hipStream_t st = (hipStream_t)p->stream;
-  if (a.total == 0) return HQC_OK;
+  uint64_t items = 0;
+  for (uint32_t s = 0; s < a.nseg; ++s) items += a.seg[s].count;
+  if (items == 0) return HQC_OK;
   int grid = p->grid;
-  if (grid <= 0) {
-    int rc = default_grid(op, mask, &grid);
+  int full = 0;
+  {
+    int rc = default_grid(op, mask, &full);
     if (rc) return rc;
   }
+  if (grid <= 0) grid = full;
+  uint32_t tile = (uint32_t)p->tile;
+  if (tile == 0) {
+    // enough tiles to give every resident workgroup one, at most 64 items each
+    uint64_t per = (items + (uint64_t)grid - 1) / (uint64_t)grid;
+    tile = (uint32_t)(per < 1 ? 1 : per > 64 ? 64 : per);
+  }
+  assign_tiles(a, tile);
   if ((uint32_t)grid > a.total) grid = (int)a.total;
   if (p->flags & HQC_F_PER_ITEM_LAUNCH) {
     // Baseline mode: the same kernel, one launch per item (count = 1).
@@ -158,6 +181,7 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
         std::memset(&one, 0, sizeof one);
         one.nseg = 1;
         one.total = 1;
+        one.tile = 1;
         hqc::SegDev &o = one.seg[0];
         o = sg;
         o.first = 0;
@@ -181,7 +205,7 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
 }
 
 int check_params(const hqc_params_t *p) {
-  if (!p || p->reserved != 0) return HQC_EINVAL;
+  if (!p || p->tile < 0 || p->tile > 64) return HQC_EINVAL;
   if (p->flags & ~(HQC_F_PER_ITEM_LAUNCH | HQC_F_GRAPH)) return HQC_EINVAL;
   if ((p->flags & HQC_F_PER_ITEM_LAUNCH) && (p->flags & HQC_F_GRAPH)) return HQC_EINVAL;
   if (p->grid < 0) return HQC_EINVAL;
@@ -258,13 +282,11 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
       sd.ks_bad = ks->bad;
     }
     mask |= (unsigned)pid_bit(segs[i].param_id);
-    sd.first = (uint32_t)total;
     total += sd.count;
     a.seg[a.nseg++] = sd;
   }
   if (total > HQC_MAX_COUNT) return HQC_ERANGE;
-  a.total = (uint32_t)total;
-  if (a.total == 0) return HQC_OK;
+  if (total == 0) return HQC_OK;
   return run(op, p, a, mask);
 }
 

@@ -1,32 +1,35 @@
 // hqc_kernels.hip -- fused HQC.PKE.Decrypt for gfx950 (CDNA4).
 //
 // One workgroup = one 64-lane wavefront.  The grid is persistent: workgroup
-// g handles items g, g + G, g + 2G, ... of the launch, whose items may come
-// from up to three parameter sets (a public, per-item property, so the
-// branch on it is uniform and data-independent).  Per item:
+// g takes tiles g, g + G, g + 2G, ... of the launch; a tile is up to 64
+// consecutive items of one parameter set (a public property of the item, so
+// the branch on it is uniform and independent of secret data).
 //
+// Per item of a tile, all 64 lanes cooperate:
 //  S0  u is staged in LDS as a bit-level doubled copy U2[t] = u[t mod n],
-//      t < 2n, so every rotation of u is a contiguous window of U2.
-//  S1  u*y (Eq. (1)): for support index y_k, output dword d of the product
-//      is the 32 bits of U2 starting at bit 32d + n - y_k, i.e. one funnel
-//      shift (v_alignbit_b32) of two adjacent U2 dwords; lane l owns the R
+//      t < 2n, so that every rotation of u is a contiguous window of U2.
+//  S1  u*y (Eq. (1)): for support index y_k, output dword d of the product is
+//      the 32 bits of U2 starting at bit 32d + n - y_k: one funnel shift
+//      (v_alignbit_b32) of two adjacent U2 dwords.  Lane l owns the R
 //      consecutive output dwords from l*R (R odd, so the 64 lanes' windows
-//      hit 64 distinct LDS banks whatever the secret offset is).
-//  S2  XOR with v (Alg. 2), into an LDS copy of v laid out one RM block per
-//      padded row.
+//      fall in distinct LDS banks whatever the secret offset is).  The next
+//      index's window is loaded while the current one is combined.
+//  S2  XOR with v, into an LDS copy of v laid out one RM block per padded row.
 //  S3-S5  one RM block per lane: bit-sliced sum of the copies, 128-point
-//      Walsh-Hadamard transform on packed 16-bit pairs in VGPRs, peak
-//      search with smallest-index tie break, sign -> symbol byte.
-//  S6-S10 Reed-Solomon with one coefficient (or position) per lane: the
-//      GF(2^8) exp/log tables live in two VGPRs per lane (4 bytes each) and
-//      are read with ds_bpermute_b32, a crossbar read whose timing does not
-//      depend on the index; syndromes, Berlekamp-Massey in 2*delta
-//      branch-free steps, error evaluator, and Chien/Forney only at the k
-//      message positions (the parity positions do not reach m).
+//      Walsh-Hadamard transform on packed 16-bit pairs in VGPRs, and a
+//      packed 16-bit peak search (magnitude, then smallest index, then
+//      sign); the symbol byte goes to the tile's symbol table in LDS.
+// Then each lane decodes the Reed-Solomon word of one item of the tile
+// (S6-S10): syndromes, Berlekamp-Massey in 2*delta steps, the error
+// evaluator, and Chien search + Forney at the k message positions only (the
+// parity positions never reach m).  GF(2^8) products go through the log and
+// exp tables, which live in two VGPRs per lane (4 bytes each) and are read
+// with ds_bpermute_b32, a crossbar read whose timing does not depend on the
+// index; a zero operand is carried as a log value >= 512 and masked.
 //
-// Constant time: loop bounds and branches depend only on the parameter set
-// and lane index; secret values flow through selects, funnel-shift amounts,
-// uniform LDS window offsets and bpermute indices only.
+// Constant time: loop bounds and branches depend only on the parameter set,
+// the tile size and loop counters; secret values flow only through selects,
+// funnel-shift amounts, uniform LDS window offsets and bpermute indices.
 #include "hqc_internal.h"
 
 namespace hqc {
@@ -38,6 +41,14 @@ template <> struct Set<1> { static constexpr int n = 17669, n1 = 46, n2 = 384, k
 template <> struct Set<3> { static constexpr int n = 35851, n1 = 56, n2 = 640, k = 24, delta = 16, w = 100; };
 template <> struct Set<5> { static constexpr int n = 57637, n1 = 90, n2 = 640, k = 32, delta = 29, w = 131; };
 
+// smallest multiple of 4 bytes >= b whose dword count is odd (so that 64
+// lanes reading the same offset of their own rows hit distinct banks)
+constexpr int odd_dword_stride(int b) {
+  int d = (b + 3) / 4;
+  return 4 * (d | 1);
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
 template <int ID> struct Geo {
   using S = Set<ID>;
   static constexpr int n = S::n, n1 = S::n1, n2 = S::n2, k = S::k, w = S::w;
@@ -46,26 +57,33 @@ template <int ID> struct Geo {
   static constexpr int W32 = n1 * n2 / 32;           // dwords of v and of the product we keep
   static constexpr int R = ((W32 + 63) / 64) | 1;    // product dwords per lane (odd)
   static constexpr int DW = n / 32;                  // dword holding bit n - 1
-  static constexpr int NB = n % 32;                  // bits of u in dword DW
+  static constexpr int NB = n % 32;                  // bits of u in that dword
   static constexpr int U_WORDS = (n + 63) / 64;
   static constexpr int V_WORDS = n1 * n2 / 64;
   static constexpr int BLK = 4 * MULT;               // dwords per RM block
   static constexpr int BSTR = BLK + 1;               // padded LDS row of a block
   static constexpr int U2 = 64 * R + DW + 2;         // doubled-u dwords (covers every window)
   static constexpr int RB = n1 * BSTR;               // received-word dwords
-  static constexpr int LDS = U2 + RB;                // LDS dwords per workgroup
   static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
-  static constexpr int SYMREG = (n1 + 63) / 64;      // VGPRs holding the symbols
+  static constexpr int SYMREG = (n1 + 63) / 64;      // blocks per lane
+  // Reed-Solomon scratch per lane (uint16 entries): reversed log-syndromes
+  // (2 TD entries, zero-padded) then the error evaluator's logs (TD entries)
+  static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 3 * TD);
+  static constexpr int RS_STR = RS_BYTES_LANE / 2;   // in uint16 entries
+  static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
+  static constexpr int A_BYTES = (cmax(4 * (U2 + RB), 64 * RS_BYTES_LANE) + 15) / 16 * 16;
+  static constexpr int LDS_BYTES = A_BYTES + 64 * SSTR;
   static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
-  static_assert(TD + 1 <= 64 && k <= 64, "one lane per RS coefficient / message byte");
+  static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");
   static_assert(n1 * n2 % 64 == 0, "v is a whole number of words");
   static_assert(64 * R >= W32, "lanes cover the product");
+  static_assert(TD + k == n1 && n1 < 255, "message positions");
 };
 
 // ---- GF(2^8) tables, x^8 + x^4 + x^3 + x^2 + 1, alpha = x ------------------
 struct GfTables {
   uint32_t exp4[64];  // bytes exp[4l .. 4l+3]; exp[255] = exp[0] = 1
-  uint32_t log4[64];  // bytes log[4l .. 4l+3]; log[0] = 0 (callers mask zero)
+  uint32_t log4[64];  // bytes log[4l .. 4l+3]; log[0] = 0 (callers mark zero)
 };
 
 constexpr GfTables make_gf_tables() {
@@ -78,7 +96,7 @@ constexpr GfTables make_gf_tables() {
     x <<= 1;
     if (x & 0x100u) x ^= 0x11Du;
   }
-  e[255] = 1;  // lets a log sum in [0, 510] be reduced by (s + (s >> 8)) & 255
+  e[255] = 1;
   for (int i = 0; i < 64; ++i) {
     t.exp4[i] = (uint32_t)e[4 * i] | (uint32_t)e[4 * i + 1] << 8 | (uint32_t)e[4 * i + 2] << 16 |
                 (uint32_t)e[4 * i + 3] << 24;
@@ -91,31 +109,51 @@ constexpr GfTables make_gf_tables() {
 __constant__ GfTables kGf = make_gf_tables();
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
+// A log value >= ZL stands for the log of zero; sums of two logs and one
+// reduction step keep it >= 512.
+constexpr uint32_t ZL = 0x400;
 
-// Table read: byte idx (0..255) of a table spread over the wave, 4 bytes per
-// lane.  Must run with all 64 lanes active.
-__device__ __forceinline__ uint32_t tab(uint32_t table4, uint32_t idx) {
-  uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(idx & 0xFCu), (int)table4);
-  return __builtin_amdgcn_ubfe(w, (idx & 3u) << 3, 8);
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+// The workgroup is one wavefront and a wavefront's LDS operations complete in
+// issue order, so ordering LDS traffic between lanes needs no s_barrier; the
+// wavefront-scope fences only stop the compiler from moving memory
+// operations across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// (s mod 255) for s in [0, 510], as an exp-table index (255 stands for 0)
-__device__ __forceinline__ uint32_t mod255(uint32_t s) { return (s + (s >> 8)) & 0xFFu; }
+// Byte idx (0..255) of a table spread over the wave, 4 bytes per lane, read
+// through the LDS crossbar (ds_bpermute_b32 selects lane idx >> 2).  Must run
+// with all 64 lanes active.  width 8 returns the byte, width 0 returns 0.
+__device__ __forceinline__ uint32_t tab(uint32_t table4, uint32_t idx, uint32_t width = 8) {
+  uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)idx, (int)table4);
+  return __builtin_amdgcn_ubfe(w, idx << 3, width);
+}
 
-__device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v ^= (uint32_t)__shfl_xor((int)v, o);
-  return v;
+// s mod 255 for s in [0, 509] (as an exp index in [0, 254])
+__device__ __forceinline__ uint32_t red255(uint32_t s) {
+  uint32_t t = s - 255u;
+  return t < s ? t : s;  // unsigned: t wraps above s when s < 255
+}
+
+// log with zero marked: log(x), or ZL (+ log[0]) when x == 0
+__device__ __forceinline__ uint32_t logz(uint32_t log4, uint32_t x) {
+  return tab(log4, x) | (x == 0 ? ZL : 0u);
+}
+
+// alpha^s for a sum of logs s (0 when s carries a zero mark)
+__device__ __forceinline__ uint32_t expz(uint32_t exp4, uint32_t s) {
+  uint32_t v = tab(exp4, red255(s) & 0xFFu);
+  return s < 512u ? v : 0u;
 }
 
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-
-__device__ __forceinline__ uint32_t from_lane(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)v);
 }
 
 // ---- S3-S5: one duplicated RM(1,7) block -> symbol byte ---------------------
@@ -139,16 +177,26 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
       p2[q] = cy & cy2;
     }
   }
-  // packed pairs (2m, 2m+1) after the first transform stage
+  // F as bytes, 4 positions per dword: B[g] byte c = F(4g + c).  A nibble
+  // of a plane spreads to the low bit of 4 bytes by one multiply.
+  uint32_t B[32];
+#pragma unroll
+  for (int g = 0; g < 32; ++g) {
+    const int q = g >> 3, sh = 4 * (g & 7);
+    uint32_t v = (__builtin_amdgcn_ubfe(p0[q], sh, 4) * 0x204081u) & 0x01010101u;
+    v += ((__builtin_amdgcn_ubfe(p1[q], sh, 4) * 0x204081u) & 0x01010101u) << 1;
+    if constexpr (MULT == 5) v += ((__builtin_amdgcn_ubfe(p2[q], sh, 4) * 0x204081u) & 0x01010101u) << 2;
+    B[g] = v;
+  }
+  // h[m] = (F(m), F(m + 64)) as 16-bit halves
   s16x2 h[64];
 #pragma unroll
   for (int m = 0; m < 64; ++m) {
-    const int q = m >> 4, b = (2 * m) & 31;
-    int f0 = (int)(((p0[q] >> b) & 1u) + 2u * ((p1[q] >> b) & 1u) + 4u * ((p2[q] >> b) & 1u));
-    int f1 = (int)(((p0[q] >> (b + 1)) & 1u) + 2u * ((p1[q] >> (b + 1)) & 1u) +
-                   4u * ((p2[q] >> (b + 1)) & 1u));
-    h[m] = s16x2{(short)(f0 + f1), (short)(f0 - f1)};
+    const uint32_t c = (uint32_t)(m & 3);
+    const uint32_t sel = c | 0x0C00u | ((4u + c) << 16) | 0x0C000000u;
+    h[m] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(B[(m >> 2) + 16], B[m >> 2], sel));
   }
+  // transform stages 1 .. 32 pair elements inside each half ...
 #pragma unroll
   for (int hh = 1; hh < 64; hh <<= 1) {
 #pragma unroll
@@ -159,211 +207,323 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
       h[m + hh] = a - c;
     }
   }
-  // H = transform of the counts; the correlation with codeword (u, sign) is
-  // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u), H'(0) = H(0) - 64*MULT.
-  h[0].x = (short)(h[0].x - 64 * MULT);
-  uint32_t best = 0;
+  // ... stage 64 pairs the two halves of each dword: (a, b) -> (a + b, a - b)
+  // as one v_pk_mad_i16: low = a*1 + b, high = b*(-1) + a
 #pragma unroll
   for (int m = 0; m < 64; ++m) {
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int u = 2 * m + half;
-      int v = half ? h[m].y : h[m].x;
-      uint32_t mag = (uint32_t)(v < 0 ? -v : v);
-      uint32_t key = (mag << 8) | (uint32_t)((127 - u) << 1) | (v > 0 ? 1u : 0u);
-      best = best > key ? best : key;
-    }
+    uint32_t x = __builtin_bit_cast(uint32_t, h[m]), d;
+    asm("v_pk_mad_i16 %0, %1, %2, %1 op_sel:[0,0,1] op_sel_hi:[1,1,0]"
+        : "=v"(d)
+        : "v"(x), "v"(0xFFFF0001u));
+    h[m] = __builtin_bit_cast(s16x2, d);
   }
-  uint32_t ustar = 127u - ((best >> 1) & 127u);
-  return ustar | ((best & 1u) << 7);  // T(u*) < 0  <=>  H'(u*) > 0
+  // H = transform of the counts.  The correlation with codeword (u, sign) is
+  // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u) with H'(0) = H(0) - 64*MULT,
+  // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
+  // Keys (16 bits): |H'| << 7 | (127 - u), |H'| <= 64*MULT <= 320.
+  h[0].x = (short)(h[0].x - 64 * MULT);
+  u16x2 kpos = {0, 0}, kneg = {0, 0};
+#pragma unroll
+  for (int m = 0; m < 64; ++m) {
+    // dword m holds u = m (low half) and u = m + 64 (high half)
+    const u16x2 idx = {(unsigned short)(127 - m), (unsigned short)(63 - m)};
+    const s16x2 zero = {0, 0};
+    s16x2 pos = __builtin_elementwise_max(h[m], zero);
+    s16x2 neg = __builtin_elementwise_max(zero - h[m], zero);
+    u16x2 kp = __builtin_bit_cast(u16x2, pos) * (unsigned short)128 + idx;
+    u16x2 kn = __builtin_bit_cast(u16x2, neg) * (unsigned short)128 + idx;
+    kpos = __builtin_elementwise_max(kpos, kp);
+    kneg = __builtin_elementwise_max(kneg, kn);
+  }
+  uint32_t bp = kpos.x > kpos.y ? kpos.x : kpos.y;
+  uint32_t bn = kneg.x > kneg.y ? kneg.x : kneg.y;
+  // keys are distinct (the index is part of them) and the peak is nonzero
+  const bool positive = bp > bn;
+  const uint32_t best = positive ? bp : bn;
+  return (127u - (best & 127u)) | (positive ? 0x80u : 0u);
 }
 
-// ---- one item ----------------------------------------------------------------
-template <int ID, int OP>
-__device__ __forceinline__ void run_item(const SegDev &sg, uint32_t item, uint32_t *lds,
-                                         uint32_t exp4, uint32_t log4) {
+// ---- S0-S2: received word r = v + (u*y)|_{n1 n2} into the padded rows -------
+
+// One item's inputs, loaded lane-strided into VGPRs ahead of use so that the
+// HBM latency of item i+1 overlaps the RM decoding of item i.
+template <int ID> struct ItemRegs {
   using G = Geo<ID>;
-  const int lane = (int)lane_id();
+  static constexpr int UREG = (G::DW + 1 + 63) / 64;  // u dwords 0 .. DW
+  static constexpr int VREG = (G::W32 + 63) / 64;
+  uint32_t u[UREG];
+  uint32_t v[VREG];
+  uint32_t y[G::YREG];
+};
+
+template <int ID, int OP>
+__device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRegs<ID> &r) {
+  using G = Geo<ID>;
+  using IR = ItemRegs<ID>;
+  const int lane = lane_id();
+  const uint32_t *vsrc = (const uint32_t *)((OP == OP_DECODE ? sg.u : sg.v) +
+                                            (size_t)item * G::V_WORDS);
+#pragma unroll
+  for (int i = 0; i < IR::VREG; ++i) {
+    const int d = lane + 64 * i;
+    r.v[i] = d < G::W32 ? vsrc[d] : 0u;
+  }
+  if constexpr (OP != OP_DECODE) {
+    const uint32_t *usrc = (const uint32_t *)(sg.u + (size_t)item * G::U_WORDS);
+#pragma unroll
+    for (int i = 0; i < IR::UREG; ++i) {
+      const int d = lane + 64 * i;
+      r.u[i] = d <= G::DW ? usrc[d] : 0u;
+    }
+    uint32_t key = 0;
+    if constexpr (OP == OP_KEYED) {
+      key = __builtin_amdgcn_readfirstlane(sg.key_ids[item]);
+      key = key < sg.ks_cap ? key : 0u;  // out-of-range ids decrypt to zeros later
+    }
+    const uint32_t *ysrc =
+        (OP == OP_KEYED) ? sg.ks_y + (size_t)key * G::w : sg.y + (size_t)item * G::w;
+#pragma unroll
+    for (int c = 0; c < G::YREG; ++c) {
+      const int idx = 64 * c + lane;
+      r.y[c] = idx < G::w ? ysrc[idx] : 0u;
+    }
+  }
+}
+
+template <int ID, int OP>
+__device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *lds) {
+  using G = Geo<ID>;
+  using IR = ItemRegs<ID>;
+  const int lane = lane_id();
   uint32_t *u2 = lds;
   uint32_t *rb = lds + G::U2;
 
-  // key slot (keyed): ids are device data; out-of-range ids decrypt to zeros
-  uint32_t key = 0;
+#pragma unroll
+  for (int i = 0; i < IR::VREG; ++i) {
+    const int d = lane + 64 * i;
+    if (d < G::W32) rb[d + d / G::BLK] = r.v[i];
+  }
+  if constexpr (OP == OP_DECODE) return;
+
+  // S0: U2[0 .. DW] = u (dword DW raw for now), then U2[DW ..] = the wrapped
+  // continuation U2[t] = u[t - n]
+#pragma unroll
+  for (int i = 0; i < IR::UREG; ++i) {
+    const int d = lane + 64 * i;
+    if (d <= G::DW) u2[d] = r.u[i];
+  }
+  // per index: sh = n - (y mod n) in [1, n]; window dword offset sh >> 5,
+  // funnel-shift amount sh & 31 (v_alignbit_b32 reads the low 5 bits)
+  uint32_t shreg[G::YREG];
+#pragma unroll
+  for (int c = 0; c < G::YREG; ++c) shreg[c] = (uint32_t)G::n - r.y[c] % (uint32_t)G::n;
+  wave_sync();
+  const uint32_t udw = u2[G::DW] & ((1u << G::NB) - 1u);
+  const uint32_t u0 = u2[0];
+  wave_sync();
+  for (int D = G::DW + lane; D < G::U2; D += 64) {
+    const int i = D - G::DW;  // >= 0
+    uint32_t val;
+    if (i == 0) {
+      val = udw | (u0 << G::NB);
+    } else {
+      const int ih = i < G::DW ? i : G::DW - 1, il = i - 1 < G::DW ? i - 1 : G::DW - 1;
+      uint32_t hi = i < G::DW ? u2[ih] : (i == G::DW ? udw : 0u);
+      uint32_t lo = i - 1 < G::DW ? u2[il] : (i - 1 == G::DW ? udw : 0u);
+      val = __builtin_amdgcn_alignbit(hi, lo, 32 - G::NB);
+    }
+    u2[D] = val;
+  }
+  wave_sync();
+
+  // S1: product, R output dwords per lane.  The windows of U consecutive
+  // indices are loaded together, then combined in order, so the later loads
+  // overlap the funnel shifts of the earlier ones.
+  uint32_t acc[G::R];
+#pragma unroll
+  for (int j = 0; j < G::R; ++j) acc[j] = 0;
+  const uint32_t *base = u2 + lane * G::R;
+  constexpr int U = G::R <= 10 ? 4 : 2;
+#pragma unroll
+  for (int c = 0; c < G::YREG; ++c) {
+    const int cnt = (G::w - 64 * c) < 64 ? (G::w - 64 * c) : 64;
+    int kk = 0;
+    for (; kk + U <= cnt; kk += U) {
+      uint32_t win[U][G::R + 1], shs[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        shs[q] = rdlane(shreg[c], kk + q);
+#pragma unroll
+        for (int j = 0; j <= G::R; ++j) win[q][j] = base[(shs[q] >> 5) + j];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+#pragma unroll
+        for (int j = 0; j < G::R; ++j)
+          acc[j] ^= __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]);
+    }
+    for (; kk < cnt; ++kk) {
+      uint32_t win[G::R + 1];
+      const uint32_t sh = rdlane(shreg[c], kk);
+#pragma unroll
+      for (int j = 0; j <= G::R; ++j) win[j] = base[(sh >> 5) + j];
+#pragma unroll
+      for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
+    }
+  }
+  // S2: r = v + (u*y) restricted to the first n1*n2 bits
+#pragma unroll
+  for (int j = 0; j < G::R; ++j) {
+    const int d = lane * G::R + j;
+    if (d < G::W32) rb[d + d / G::BLK] ^= acc[j];
+  }
+}
+
+// ---- S6-S10: Reed-Solomon decode of one item per lane ------------------------
+template <int ID, int OP>
+__device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool active,
+                                        const uint8_t *cs, uint16_t *my, uint32_t exp4,
+                                        uint32_t log4) {
+  using G = Geo<ID>;
+  constexpr int TD = G::TD;
+
+  // S6: S_{i+1} = sum_j c_j alpha^((i+1) j); exponent stepped by j per i
+  uint32_t S[TD];
+#pragma unroll
+  for (int i = 0; i < TD; ++i) S[i] = 0;
+#pragma unroll 1
+  for (int j = 0; j < G::n1; ++j) {
+    const uint32_t c = cs[j];
+    const uint32_t width = c ? 8u : 0u;
+    uint32_t e = tab(log4, c);
+#pragma unroll
+    for (int i = 0; i < TD; ++i) {
+      e = red255(e + (uint32_t)j);
+      S[i] ^= tab(exp4, e, width);
+    }
+  }
+  // reversed log-syndromes: my[m] = log S_{TD-m} (m < TD), zero marks after
+#pragma unroll
+  for (int m = 0; m < TD; ++m) my[m] = (uint16_t)logz(log4, S[TD - 1 - m]);
+#pragma unroll
+  for (int m = TD; m < 2 * TD; ++m) my[m] = (uint16_t)ZL;
+
+  // S7: Berlekamp-Massey, B' = x^s B / b kept as logs (lb).  After step r,
+  // deg Lambda <= r and deg B' <= r + 1, so step r touches i <= r + 1 only.
+  uint32_t lam[TD + 1], lb[TD + 1];
+#pragma unroll
+  for (int i = 0; i <= TD; ++i) {
+    lam[i] = i == 0 ? 1u : 0u;
+    lb[i] = i == 1 ? 0u : ZL;
+  }
+  uint32_t L = 0;
+#pragma unroll 1
+  for (int r = 1; r <= TD; ++r) {
+    const uint16_t *sp = my + (TD - r);  // sp[i] = log S_{r-i} (zero mark when i >= r)
+    uint32_t delta = 0;
+#pragma unroll
+    for (int i = 0; i <= TD; ++i)
+      if (i < r) delta ^= expz(exp4, logz(log4, lam[i]) + sp[i]);
+    const uint32_t lD = logz(log4, delta);
+    const bool swap = delta != 0 && 2 * L <= (uint32_t)(r - 1);
+    const uint32_t nlD = 255u - (lD & 0xFFu);
+#pragma unroll
+    for (int i = TD; i >= 0; --i) {
+      if (i <= r + 1) {
+        if (i <= r) lam[i] ^= expz(exp4, lD + lb[i]);
+        if (i >= 1) {
+          // B'_new[i] = x * (swap ? Lambda_old / Delta : B')[i - 1]; lam[i-1]
+          // is still the old coefficient (the loop runs downwards)
+          const uint32_t q = i - 1 < r ? red255(logz(log4, lam[i - 1]) + nlD) : ZL;
+          lb[i] = swap ? q : lb[i - 1];
+        } else {
+          lb[0] = ZL;
+        }
+      }
+    }
+    L = swap ? (uint32_t)r - L : L;
+  }
+
+  // final logs of Lambda
+  uint32_t ll[TD + 1];
+#pragma unroll
+  for (int i = 0; i <= TD; ++i) ll[i] = logz(log4, lam[i]);
+
+  // S9 (part): Omega = S(x) Lambda(x) mod x^TD; my[2 TD + e] = log Omega_e
+#pragma unroll 1
+  for (int e = 0; e < TD; ++e) {
+    const uint16_t *sp = my + (TD - e - 1);  // sp[i] = log S_{e+1-i}
+    uint32_t om = 0;
+#pragma unroll
+    for (int i = 0; i <= TD; ++i)
+      if (i <= e) om ^= expz(exp4, ll[i] + sp[i]);
+    my[2 * TD + e] = (uint16_t)logz(log4, om);
+  }
+
+  // S8-S10: Chien + Forney at message position j = TD + t, then m_t
+  const uint16_t *lom = my + 2 * TD;
+#pragma unroll 1
+  for (int t = 0; t < G::k; ++t) {
+    const uint32_t j = (uint32_t)(TD + t);
+    uint32_t ex = 0;  // (-i j) mod 255
+    uint32_t lamv = 0, oddv = 0, omv = 0;
+#pragma unroll
+    for (int i = 0; i <= TD; ++i) {
+      if (i > 0) ex = red255(ex + 255u - j);
+      const uint32_t tl = expz(exp4, ll[i] + ex);
+      lamv ^= tl;
+      if (i & 1) oddv ^= tl;
+      if (i < TD) omv ^= expz(exp4, lom[i] + ex);
+    }
+    // e_j = Omega(X^-1) / Lambda'(X^-1) with Lambda'(X^-1) = X * odd(X^-1), X = alpha^j
+    const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
+    uint32_t e = tab(exp4, red255(x + 255u - j));
+    e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
+    uint32_t mb = (cs[j] ^ e) & 0xFFu;
+    if (active) sg.m[(size_t)item * G::k + t] = (uint8_t)mb;
+  }
+}
+
+template <int ID, int OP>
+__device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
+                                         uint32_t exp4, uint32_t log4) {
+  using G = Geo<ID>;
+  const int lane = lane_id();
+  uint8_t *sym = (uint8_t *)lds + G::A_BYTES;
+  ItemRegs<ID> regs;
+  prefetch<ID, OP>(sg, item0, regs);
+  for (int it = 0; it < nt; ++it) {
+    received_word<ID, OP>(regs, lds);
+    wave_sync();
+    if (it + 1 < nt) prefetch<ID, OP>(sg, item0 + (uint32_t)it + 1, regs);
+    const uint32_t *rb = lds + G::U2;
+#pragma unroll
+    for (int pass = 0; pass < G::SYMREG; ++pass) {
+      const int j = lane + 64 * pass;
+      const int jj = j < G::n1 ? j : G::n1 - 1;
+      const uint32_t sbyte = rm_decode_block<G::MULT>(rb + jj * G::BSTR);
+      if (j < G::n1) sym[it * G::SSTR + j] = (uint8_t)sbyte;
+    }
+    wave_sync();
+  }
+  // one Reed-Solomon word per lane; lanes past the tile decode a copy of its
+  // first item and store nothing
+  const int slot = lane < nt ? lane : 0;
+  const uint32_t item = item0 + (uint32_t)slot;
+  bool active = lane < nt;
   bool bad_key = false;
   if constexpr (OP == OP_KEYED) {
-    key = __builtin_amdgcn_readfirstlane(sg.key_ids[item]);
-    bad_key = key >= sg.ks_cap;
-    key = bad_key ? 0u : key;
+    bad_key = sg.key_ids[item] >= sg.ks_cap;
   }
-
-  // S2 input: v (decrypt) or r (decode), one padded row per RM block
-  const uint32_t *vsrc = (const uint32_t *)((OP == OP_DECODE ? sg.u : sg.v) +
-                                            (size_t)item * G::V_WORDS);
-  for (int d = lane; d < G::W32; d += 64) rb[d + d / G::BLK] = vsrc[d];
-
-  if constexpr (OP != OP_DECODE) {
-    // S0: U2[0 .. DW) = u, then U2[DW ..] = the wrapped continuation
-    const uint32_t *usrc = (const uint32_t *)(sg.u + (size_t)item * G::U_WORDS);
-    for (int d = lane; d < G::DW; d += 64) u2[d] = usrc[d];
-    const uint32_t udw = __builtin_amdgcn_readfirstlane(usrc[G::DW]) & ((1u << G::NB) - 1u);
-    const uint32_t *ysrc = (OP == OP_KEYED) ? sg.ks_y + (size_t)key * G::w : sg.y + (size_t)item * G::w;
-    uint32_t yreg[G::YREG];
-#pragma unroll
-    for (int c = 0; c < G::YREG; ++c) {
-      int idx = 64 * c + lane;
-      yreg[c] = idx < G::w ? ysrc[idx] : 0u;
-    }
-    __syncthreads();
-    for (int D = G::DW + lane; D < G::U2; D += 64) {
-      const int i = D - G::DW;  // >= 0
-      uint32_t val;
-      if (i == 0) {
-        val = udw | (u2[0] << G::NB);
-      } else {
-        const int ih = i < G::DW ? i : G::DW - 1, il = i - 1 < G::DW ? i - 1 : G::DW - 1;
-        uint32_t hi = i < G::DW ? u2[ih] : (i == G::DW ? udw : 0u);
-        uint32_t lo = i - 1 < G::DW ? u2[il] : (i - 1 == G::DW ? udw : 0u);
-        val = __builtin_amdgcn_alignbit(hi, lo, 32 - G::NB);
-      }
-      u2[D] = val;
-    }
-    __syncthreads();
-
-    // S1: product, R output dwords per lane
-    uint32_t acc[G::R];
-#pragma unroll
-    for (int j = 0; j < G::R; ++j) acc[j] = 0;
-    const uint32_t *base = u2 + lane * G::R;
-#pragma unroll
-    for (int c = 0; c < G::YREG; ++c) {
-      const int cnt = (G::w - 64 * c) < 64 ? (G::w - 64 * c) : 64;
-      for (int kk = 0; kk < cnt; ++kk) {
-        uint32_t yk = rdlane(yreg[c], kk) % (uint32_t)G::n;
-        uint32_t sh = (uint32_t)G::n - yk;  // in [1, n]
-        const uint32_t *p = base + (sh >> 5);
-        const uint32_t s = sh & 31u;
-        uint32_t win[G::R + 1];
-#pragma unroll
-        for (int j = 0; j <= G::R; ++j) win[j] = p[j];
-#pragma unroll
-        for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], s);
-      }
-    }
-    // S2: r = v + (u*y) restricted to the first n1*n2 bits
-#pragma unroll
-    for (int j = 0; j < G::R; ++j) {
-      const int d = lane * G::R + j;
-      if (d < G::W32) rb[d + d / G::BLK] ^= acc[j];
-    }
-  }
-  __syncthreads();
-
-  // S3-S5: RM blocks, one per lane
-  uint32_t sym[G::SYMREG];
-#pragma unroll
-  for (int pass = 0; pass < G::SYMREG; ++pass) {
-    int j = lane + 64 * pass;
-    int jj = j < G::n1 ? j : G::n1 - 1;
-    sym[pass] = rm_decode_block<G::MULT>(rb + jj * G::BSTR);
-  }
-
-  // S6: syndromes, lane i holds S_i (i = 1 .. TD)
-  uint32_t logc[G::SYMREG];
-#pragma unroll
-  for (int pass = 0; pass < G::SYMREG; ++pass) logc[pass] = tab(log4, sym[pass]);
-  uint32_t S = 0, ij = 0;
-  const uint32_t il = (uint32_t)lane;
-#pragma unroll
-  for (int pass = 0; pass < G::SYMREG; ++pass) {
-    const int cnt = (G::n1 - 64 * pass) < 64 ? (G::n1 - 64 * pass) : 64;
-    for (int j = 0; j < cnt; ++j) {
-      uint32_t lc = rdlane(logc[pass], j);
-      uint32_t cz = rdlane(sym[pass], j);
-      uint32_t t = tab(exp4, mod255(lc + ij));
-      S ^= cz ? t : 0u;
-      ij += il;
-      ij = ij >= 255u ? ij - 255u : ij;
-    }
-  }
-  S = (lane >= 1 && lane <= G::TD) ? S : 0u;
-
-  // S7: Berlekamp-Massey with B' = x^s B / b (lane i holds coefficient i)
-  const uint32_t logS = tab(log4, S) | (S == 0 ? 0x100u : 0u);
-  uint32_t lam = lane == 0 ? 1u : 0u;
-  uint32_t bb = lane == 1 ? 1u : 0u;
-  int L = 0;
-  for (int r = 1; r <= G::TD; ++r) {
-    const int src = r - lane;
-    const bool valid = src >= 1;
-    const uint32_t lS = from_lane(logS, valid ? src : 0);
-    const uint32_t lL = tab(log4, lam);
-    uint32_t term = tab(exp4, mod255(lL + (lS & 0xFFu)));
-    term = (valid && lam != 0 && !(lS & 0x100u)) ? term : 0u;
-    const uint32_t delta = __builtin_amdgcn_readfirstlane(wave_xor(term));
-    const uint32_t lD = tab(log4, delta);
-    const bool nz = delta != 0;
-    const uint32_t lB = tab(log4, bb);
-    uint32_t t1 = tab(exp4, mod255(lD + lB));
-    t1 = (nz && bb != 0) ? t1 : 0u;
-    uint32_t q = tab(exp4, mod255(lL + 255u - lD));
-    q = (nz && lam != 0) ? q : 0u;
-    const bool swap = nz && (2 * L <= r - 1);
-    const uint32_t pre = swap ? q : bb;
-    const uint32_t up = from_lane(pre, lane > 0 ? lane - 1 : 0);
-    bb = (lane >= 1 && lane <= G::TD) ? up : 0u;
-    lam = lane <= G::TD ? (lam ^ t1) : 0u;
-    L = swap ? r - L : L;
-  }
-
-  // S9 (part): Omega = S(x) Lambda(x) mod x^TD, lane e holds Omega_e
-  const uint32_t lLam = tab(log4, lam);
-  uint32_t om = 0;
-  for (int i = 0; i <= G::TD; ++i) {
-    const uint32_t li = rdlane(lLam, i);
-    const uint32_t zi = rdlane(lam, i);
-    const int src = lane + 1 - i;
-    const bool valid = src >= 1 && src <= G::TD;
-    const uint32_t lS = from_lane(logS, valid ? src : 0);
-    uint32_t t = tab(exp4, mod255(li + (lS & 0xFFu)));
-    om ^= (valid && zi != 0 && !(lS & 0x100u)) ? t : 0u;
-  }
-  om = lane < G::TD ? om : 0u;
-
-  // S8-S10: Chien + Forney at message position j = TD + lane
-  const uint32_t lOm = tab(log4, om);
-  const uint32_t jm = (uint32_t)(G::TD + (lane < G::k ? lane : 0));  // < 255
-  uint32_t ex = 0;  // (-i j) mod 255
-  uint32_t lamv = 0, oddv = 0, omv = 0;
-  for (int i = 0; i <= G::TD; ++i) {
-    const uint32_t li = rdlane(lLam, i), zi = rdlane(lam, i);
-    uint32_t t = tab(exp4, mod255(li + ex));
-    t = zi ? t : 0u;
-    lamv ^= t;
-    oddv ^= (i & 1) ? t : 0u;
-    if (i < G::TD) {
-      const uint32_t lo = rdlane(lOm, i), zo = rdlane(om, i);
-      uint32_t t2 = tab(exp4, mod255(lo + ex));
-      omv ^= zo ? t2 : 0u;
-    }
-    ex = ex >= jm ? ex - jm : ex + 255u - jm;
-  }
-  // e_j = Omega(X^-1) / Lambda'(X^-1), Lambda'(X^-1) = X * odd part of Lambda at X^-1
-  const uint32_t l1 = mod255(tab(log4, omv) + 255u - tab(log4, oddv));
-  uint32_t e = tab(exp4, mod255(l1 + 255u - jm));
-  e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
-  const int j = G::TD + lane;
-  uint32_t cj = from_lane(sym[0], j < 64 ? j : 0);
-  if constexpr (G::SYMREG > 1) {
-    const uint32_t c1 = from_lane(sym[G::SYMREG - 1], j >= 64 ? j - 64 : 0);
-    cj = j >= 64 ? c1 : cj;
-  }
-  uint32_t mbyte = (cj ^ e) & 0xFFu;
-  if constexpr (OP == OP_KEYED) mbyte = bad_key ? 0u : mbyte;
-  if (lane < G::k) sg.m[(size_t)item * G::k + lane] = (uint8_t)mbyte;
+  uint16_t *my = (uint16_t *)lds + lane * G::RS_STR;
+  rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
   if constexpr (OP == OP_KEYED) {
-    if (bad_key && lane == 0) atomicAdd(sg.ks_bad, 1ull);
+    if (active && bad_key) {
+      for (int t = 0; t < G::k; ++t) sg.m[(size_t)item * G::k + t] = 0;
+      atomicAdd(sg.ks_bad, 1ull);
+    }
   }
-  __syncthreads();
+  wave_sync();
 }
 
 template <int OP, unsigned MASK>
@@ -376,10 +536,12 @@ __global__ __launch_bounds__(64) void hqc_kernel(KArgs a) {
     if (a.nseg > 1 && unit >= a.seg[1].first) s = 1;
     if (a.nseg > 2 && unit >= a.seg[2].first) s = 2;
     const SegDev &sg = a.seg[s];
-    const uint32_t item = unit - sg.first;
-    if ((MASK & 1u) && sg.pid == 1) run_item<1, OP>(sg, item, lds, exp4, log4);
-    if ((MASK & 2u) && sg.pid == 3) run_item<3, OP>(sg, item, lds, exp4, log4);
-    if ((MASK & 4u) && sg.pid == 5) run_item<5, OP>(sg, item, lds, exp4, log4);
+    const uint32_t item0 = (unit - sg.first) * a.tile;
+    const uint32_t left = sg.count - item0;
+    const int nt = (int)(left < a.tile ? left : a.tile);
+    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP>(sg, item0, nt, lds, exp4, log4);
   }
 }
 
@@ -404,7 +566,7 @@ template <int ID> void fill_info(SetInfo *o) {
   o->mult = G::MULT;
   o->u_words = G::U_WORDS;
   o->v_words = G::V_WORDS;
-  o->lds_bytes = sizeof(uint32_t) * G::LDS;
+  o->lds_bytes = G::LDS_BYTES;
 }
 
 }  // namespace

@@ -50,7 +50,7 @@ class Sizes(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("param_id", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32)]
 
 
 class Segment(ctypes.Structure):
@@ -112,8 +112,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _params(pid, flags, grid, stream):
-    return Params(pid, flags, _stream(stream), grid, 0)
+def _params(pid, flags, grid, stream, tile=0):
+    return Params(pid, flags, _stream(stream), grid, tile)
 
 
 def _dev(t, dtype, name, shape=None):
@@ -134,12 +134,12 @@ def _out(out, count, k, device):
     return out
 
 
-def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None):
+def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None, tile=0):
     """m[i] = HQC.PKE.Decrypt(y[i], (u[i], v[i])) for every row (Alg. 2)."""
     s = sizes(pid)
     count = u.shape[0]
     out = _out(out, count, s["k"], u.device)
-    p = _params(pid, flags, grid, stream)
+    p = _params(pid, flags, grid, stream, tile)
     rc = lib().hqc_decrypt_batch(
         ctypes.byref(p), _dev(u, torch.int64, "u", (count, s["u_words"])),
         _dev(v, torch.int64, "v", (count, s["v_words"])),
@@ -149,12 +149,12 @@ def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None):
     return out
 
 
-def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None):
+def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None, tile=0):
     """m[i] = C.Decode(r[i]) (the concatenated decoder alone)."""
     s = sizes(pid)
     count = r.shape[0]
     out = _out(out, count, s["k"], r.device)
-    p = _params(pid, flags, grid, stream)
+    p = _params(pid, flags, grid, stream, tile)
     rc = lib().hqc_decode_batch(ctypes.byref(p), _dev(r, torch.int64, "r", (count, s["v_words"])),
                                 _dev(out, torch.uint8, "out", (count, s["k"])), count)
     _check(rc, "hqc_decode_batch")
@@ -181,19 +181,19 @@ def _segments(items, decode):
     return segs, outs
 
 
-def decrypt_mixed(items, flags=0, grid=0, stream=None):
+def decrypt_mixed(items, flags=0, grid=0, stream=None, tile=0):
     """One launch over several parameter sets.  items: list of dicts with
     pid, u, v, y (and optionally out); returns the list of outputs."""
     segs, outs = _segments(items, decode=False)
-    p = _params(0, flags, grid, stream)
+    p = _params(0, flags, grid, stream, tile)
     _check(lib().hqc_decrypt_mixed(ctypes.byref(p), segs, len(items)), "hqc_decrypt_mixed")
     return outs
 
 
-def decode_mixed(items, flags=0, grid=0, stream=None):
+def decode_mixed(items, flags=0, grid=0, stream=None, tile=0):
     """items: list of dicts with pid, r (and optionally out)."""
     segs, outs = _segments(items, decode=True)
-    p = _params(0, flags, grid, stream)
+    p = _params(0, flags, grid, stream, tile)
     _check(lib().hqc_decode_mixed(ctypes.byref(p), segs, len(items)), "hqc_decode_mixed")
     return outs
 
@@ -239,12 +239,12 @@ class KeyStore:
             pass
 
 
-def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, stream=None):
+def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, stream=None, tile=0):
     """decrypt_batch with y[i] = slot key_ids[i] of the keystore."""
     s = sizes(pid)
     count = u.shape[0]
     out = _out(out, count, s["k"], u.device)
-    p = _params(pid, flags, grid, stream)
+    p = _params(pid, flags, grid, stream, tile)
     rc = lib().hqc_decrypt_batch_keyed(
         ctypes.byref(p), ks.handle, _dev(u, torch.int64, "u", (count, s["u_words"])),
         _dev(v, torch.int64, "v", (count, s["v_words"])),
