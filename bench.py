@@ -10,6 +10,7 @@ per-launch latency percentiles, the roofline of the kernel and the CPU
 checker's rate on the host cores.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -97,6 +98,42 @@ def time_per_item(hqc, pid, u, v, y, out):
     return time.perf_counter() - t0
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_12904_amd", "csrc", "hqc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hqc1_b65536.json")
+
+
+def kernel_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-kernel calibration), if they were taken on
+    the kernel source as it is now; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(mib, device):
+    """A plain device-to-device copy of mib MiB (one read + one write of the
+    buffer): the reference for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.int64, device=device)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def pct(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
@@ -143,6 +180,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU checker baseline")
     ap.add_argument("--no-per-item", action="store_true", help="skip the per-launch baseline")
     ap.add_argument("--sets", default="1,3,5")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decryption batch has no cross-GPU step; "
@@ -156,6 +195,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hqc.lib()
+    if args.calibrate_copy:
+        copy_calibration(args.calibrate_copy, dev)
     sets = [int(x) for x in args.sets.split(",")]
     results = {}
     for pid in sets:
@@ -203,7 +244,9 @@ def main():
         "per_set": {"HQC-%d" % k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                    for kk, vv in r.items()} for k, r in results.items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
-                     "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS, "traffic": None,
+                     "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS,
+                     "traffic": measured_traffic() if (pid0 == 1 and args.count == 65536) else None,
+                     "traffic_algorithmic": hbm_bytes(pid0) * args.count,
                      "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
                      "kernel_ms": main_r["ms_mean"]},
     }
