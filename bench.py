@@ -75,14 +75,14 @@ def time_batched(hqc, pid, u, v, y, out, steps, warmup):
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream)
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
-        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream)
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE)
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -97,6 +97,9 @@ def time_per_item(hqc, pid, u, v, y, out):
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
+
+GRID = 0  # launch knobs (0 = the library's choice); set from the command line
+TILE = 0
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_12904_amd", "csrc", "hqc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hqc1_b65536.json")
@@ -171,6 +174,40 @@ def cpu_baseline(seconds_target=12.0):
             "recovered_m": ok}, (pid, y, u, v, m)
 
 
+def serving_bench(device, loads, seconds, streams=4, budget=1 << 30):
+    """Poisson arrivals of decryption requests (parameter set 50/30/20 %,
+    b uniform in 1..4096 ciphertexts under one key, 10,000 device-resident
+    keys split 5,000 / 3,000 / 2,000) at each offered load in decrypts/s;
+    latency from arrival to the messages on the host."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import hqc, serve, synth
+    counts = {1: 5000, 3: 3000, 5: 2000}
+    ks = hqc.KeyStore(counts[1], counts[3], counts[5])
+    pools, rows = {}, {}
+    for pid in (1, 3, 5):
+        s = dict(SETS[pid])
+        _, _, y = synth.keys(0x5E00 + pid, pid, s, counts[pid])
+        ks.put(pid, 0, y)
+        rows[pid] = 8192
+        u = synth.words(0x5E10 + pid, (rows[pid], (s["n"] + 63) // 64))
+        v = synth.words(0x5E20 + pid, (rows[pid], s["n1"] * s["n2"] // 64))
+        pools[pid] = (torch.from_numpy(u.view(np.int64)).pin_memory(),
+                      torch.from_numpy(v.view(np.int64)).pin_memory())
+    srv = serve.Server(ks, pools, streams=streams, budget_bytes=budget, device=device)
+    # warm the slots (graph-free launches, allocator, copies)
+    srv.run(serve.poisson_requests(2e6, 0.05, counts, 1, pool_rows=rows), realtime=False)
+    out = {}
+    for load in loads:
+        reqs = serve.poisson_requests(load, seconds, counts, int(load) & 0xFFFF, pool_rows=rows)
+        wall = srv.run(reqs)
+        st = serve.latency_stats(reqs, wall)
+        st["offered_decrypts_per_s"] = load
+        out["%.0e" % load] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    ks.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +219,10 @@ def main():
     ap.add_argument("--sets", default="1,3,5")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of MIB MiB (counter calibration)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop run")
+    ap.add_argument("--serving-seconds", type=float, default=2.0)
+    ap.add_argument("--tile", type=int, default=0, help="items per workgroup (0 = library)")
+    ap.add_argument("--grid", type=int, default=0, help="persistent workgroups (0 = library)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decryption batch has no cross-GPU step; "
@@ -192,6 +233,8 @@ def main():
     import torch
     from paper_2512_12904_amd import hqc
 
+    global GRID, TILE
+    GRID, TILE = args.grid, args.tile
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hqc.lib()
@@ -253,6 +296,9 @@ def main():
     if not args.no_per_item:
         line["per_item_decrypts_per_s"] = main_r["per_item_decrypts_per_s"]
         line["batched_over_per_item"] = main_r["batched_over_per_item"]
+    if not args.no_serving:
+        line["serving"] = serving_bench(dev, (1e5, 1e6, 1e7), args.serving_seconds)
+        line["p99_latency_ms_serving_1e6"] = line["serving"]["1e+06"]["p99_ms"]
     if not args.no_cpu:
         cb, sample = cpu_baseline()
         # same run: the GPU decrypts the checker's sample and must agree bitwise
