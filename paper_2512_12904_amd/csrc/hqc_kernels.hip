@@ -152,6 +152,14 @@ __device__ __forceinline__ uint32_t expz(uint32_t exp4, uint32_t s) {
   return s < 512u ? v : 0u;
 }
 
+// three-input bitwise functions (v_bitop3_b32, truth table over the inputs)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
@@ -164,14 +172,14 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     uint32_t a = blk[q], b = blk[4 + q], c = blk[8 + q];
-    uint32_t s = a ^ b ^ c, cy = (a & b) | (c & (a ^ b));
+    uint32_t s = xor3(a, b, c), cy = maj3(a, b, c);
     if constexpr (MULT == 3) {
       p0[q] = s;
       p1[q] = cy;
       p2[q] = 0;
     } else {
       uint32_t d = blk[12 + q], e = blk[16 + q];
-      uint32_t s2 = s ^ d ^ e, cy2 = (s & d) | (e & (s ^ d));
+      uint32_t s2 = xor3(s, d, e), cy2 = maj3(s, d, e);
       p0[q] = s2;
       p1[q] = cy ^ cy2;
       p2[q] = cy & cy2;
@@ -188,6 +196,7 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
     if constexpr (MULT == 5) v += ((__builtin_amdgcn_ubfe(p2[q], sh, 4) * 0x204081u) & 0x01010101u) << 2;
     B[g] = v;
   }
+  __builtin_amdgcn_sched_barrier(0);
   // h[m] = (F(m), F(m + 64)) as 16-bit halves
   s16x2 h[64];
 #pragma unroll
@@ -196,6 +205,7 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
     const uint32_t sel = c | 0x0C00u | ((4u + c) << 16) | 0x0C000000u;
     h[m] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(B[(m >> 2) + 16], B[m >> 2], sel));
   }
+  __builtin_amdgcn_sched_barrier(0);
   // transform stages 1 .. 32 pair elements inside each half ...
 #pragma unroll
   for (int hh = 1; hh < 64; hh <<= 1) {
@@ -222,6 +232,7 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
   // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
   // Keys (16 bits): |H'| << 7 | (127 - u), |H'| <= 64*MULT <= 320.
   h[0].x = (short)(h[0].x - 64 * MULT);
+  __builtin_amdgcn_sched_barrier(0);
   u16x2 kpos = {0, 0}, kneg = {0, 0};
 #pragma unroll
   for (int m = 0; m < 64; ++m) {
@@ -356,11 +367,13 @@ __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *l
 #pragma unroll
         for (int j = 0; j <= G::R; ++j) win[q][j] = base[(shs[q] >> 5) + j];
       }
+      // two indices per three-way XOR
 #pragma unroll
-      for (int q = 0; q < U; ++q)
+      for (int q = 0; q < U; q += 2)
 #pragma unroll
         for (int j = 0; j < G::R; ++j)
-          acc[j] ^= __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]);
+          acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
+                        __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
     }
     for (; kk < cnt; ++kk) {
       uint32_t win[G::R + 1];
@@ -387,20 +400,36 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
   using G = Geo<ID>;
   constexpr int TD = G::TD;
 
-  // S6: S_{i+1} = sum_j c_j alpha^((i+1) j); exponent stepped by j per i
+  // S6: S_i = sum_j c_j alpha^(i j), in groups of SG syndromes so that only
+  // SG accumulators and SG table reads are in flight; within a group the
+  // exponent log c_j + i j steps by j per syndrome
+  constexpr int SG = 10;
   uint32_t S[TD];
 #pragma unroll
-  for (int i = 0; i < TD; ++i) S[i] = 0;
-#pragma unroll 1
-  for (int j = 0; j < G::n1; ++j) {
-    const uint32_t c = cs[j];
-    const uint32_t width = c ? 8u : 0u;
-    uint32_t e = tab(log4, c);
+  for (int g0 = 0; g0 < TD; g0 += SG) {
+    const int gn = TD - g0 < SG ? TD - g0 : SG;
+    uint32_t acc[SG];
 #pragma unroll
-    for (int i = 0; i < TD; ++i) {
-      e = red255(e + (uint32_t)j);
-      S[i] ^= tab(exp4, e, width);
+    for (int i = 0; i < SG; ++i) acc[i] = 0;
+    uint32_t gj = 0;  // (g0 * j) mod 255
+#pragma unroll 1
+    for (int j = 0; j < G::n1; ++j) {
+      const uint32_t c = cs[j];
+      const uint32_t width = c ? 8u : 0u;
+      uint32_t e = red255(tab(log4, c) + gj);  // log c_j + g0 j
+#pragma unroll
+      for (int i = 0; i < SG; ++i) {
+        if (i < gn) {
+          e = red255(e + (uint32_t)j);
+          acc[i] ^= tab(exp4, e, width);
+        }
+      }
+      gj = red255(gj + (uint32_t)g0);
     }
+#pragma unroll
+    for (int i = 0; i < SG; ++i)
+      if (i < gn) S[g0 + i] = acc[i];
+    wave_sync();  // keeps the groups apart in the schedule
   }
   // reversed log-syndromes: my[m] = log S_{TD-m} (m < TD), zero marks after
 #pragma unroll
