@@ -439,7 +439,10 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 
   // S7: Berlekamp-Massey, B' = x^s B / b kept as logs (lb).  After step r,
   // deg Lambda <= r and deg B' <= r + 1, so step r touches i <= r + 1 only.
-  uint32_t lam[TD + 1], lb[TD + 1];
+  // For the smaller sets the logs of Lambda found for the discrepancy are
+  // kept for the update; for HQC-5 they are recomputed to save registers.
+  constexpr bool KEEP_LL = TD <= 32;
+  uint32_t lam[TD + 1], lb[TD + 1], llk[KEEP_LL ? TD + 1 : 1];
 #pragma unroll
   for (int i = 0; i <= TD; ++i) {
     lam[i] = i == 0 ? 1u : 0u;
@@ -451,8 +454,13 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
     const uint16_t *sp = my + (TD - r);  // sp[i] = log S_{r-i} (zero mark when i >= r)
     uint32_t delta = 0;
 #pragma unroll
-    for (int i = 0; i <= TD; ++i)
-      if (i < r) delta ^= expz(exp4, logz(log4, lam[i]) + sp[i]);
+    for (int i = 0; i <= TD; ++i) {
+      if (i < r) {
+        const uint32_t li = logz(log4, lam[i]);
+        if constexpr (KEEP_LL) llk[i] = li;
+        delta ^= expz(exp4, li + sp[i]);
+      }
+    }
     const uint32_t lD = logz(log4, delta);
     const bool swap = delta != 0 && 2 * L <= (uint32_t)(r - 1);
     const uint32_t nlD = 255u - (lD & 0xFFu);
@@ -463,7 +471,11 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
         if (i >= 1) {
           // B'_new[i] = x * (swap ? Lambda_old / Delta : B')[i - 1]; lam[i-1]
           // is still the old coefficient (the loop runs downwards)
-          const uint32_t q = i - 1 < r ? red255(logz(log4, lam[i - 1]) + nlD) : ZL;
+          uint32_t q = ZL;
+          if (i - 1 < r) {
+            const uint32_t li = KEEP_LL ? llk[KEEP_LL ? i - 1 : 0] : logz(log4, lam[i - 1]);
+            q = red255(li + nlD);
+          }
           lb[i] = swap ? q : lb[i - 1];
         } else {
           lb[0] = ZL;
