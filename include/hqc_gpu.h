@@ -154,6 +154,21 @@ int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks
                             const uint64_t *u, const uint64_t *v,
                             const uint32_t *key_ids, uint8_t *m_out, size_t count);
 
+/* Key generation, Alg. 3 (the randomness is an input): s[i] = x[i] + h[i]*y[i]
+ * in GF(2)[X]/(X^n - 1).  h, s_out: count * u_words; x, y: count * w.
+ * Indices are taken mod n; s_out bits >= n are zero. */
+int hqc_keygen_batch(const hqc_params_t *params, const uint64_t *h, const uint32_t *x,
+                     const uint32_t *y, uint64_t *s_out, size_t count);
+
+/* Encryption, Alg. 1, with the public key (h[i], s[i]) of item i and the
+ * randomness as input: u = r1 + h*r2, v = the first n1*n2 bits of
+ * mG + s*r2 + e, mG the concatenated code of m (Sec. II-A).
+ * h, s, u_out: count * u_words; m: count * k; r1, r2: count * wr;
+ * e: count * we; v_out: count * v_words. */
+int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                      const uint8_t *m, const uint32_t *r1, const uint32_t *r2,
+                      const uint32_t *e, uint64_t *u_out, uint64_t *v_out, size_t count);
+
 /* Static text for an HQC_* code. */
 const char *hqc_strerror(int code);
 /* hipError_t of the last HQC_EHIP on this thread (0 if none). */

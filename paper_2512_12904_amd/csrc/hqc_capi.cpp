@@ -447,6 +447,88 @@ int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks
   return run_segments(hqc::OP_KEYED, params, &s, 1, ks, key_ids);
 }
 
+static int run_encrypt(bool encrypt, const hqc_params_t *params, const hqc::EncArgs &a) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  int grid = params->grid;
+  if (grid <= 0) {
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, hqc::encrypt_kernel_ptr(encrypt, params->param_id), 64,
+          hqc::encrypt_lds_bytes(params->param_id));
+    if (e != hipSuccess) return hip_fail(e);
+    grid = cus * (per_cu < 1 ? 1 : per_cu);
+  }
+  if ((uint32_t)grid > a.count) grid = (int)a.count;
+  e = hqc::launch_encrypt(encrypt, params->param_id, a, grid, (hipStream_t)params->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
+int hqc_keygen_batch(const hqc_params_t *params, const uint64_t *h, const uint32_t *x,
+                     const uint32_t *y, uint64_t *s_out, size_t count) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count == 0) return HQC_OK;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  const size_t c = count, uw = (size_t)si.u_words * 8, yw = (size_t)si.w * 4;
+  if (!aligned(h, 8) || !aligned(s_out, 8) || !aligned(x, 4) || !aligned(y, 4)) return HQC_EINVAL;
+  if (!in_device_allocation(h, c * uw) || !in_device_allocation(s_out, c * uw) ||
+      !in_device_allocation(x, c * yw) || !in_device_allocation(y, c * yw))
+    return HQC_EINVAL;
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.h = h;
+  a.x = x;
+  a.y = y;
+  a.s_out = s_out;
+  a.count = (uint32_t)count;
+  return run_encrypt(false, params, a);
+}
+
+int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                      const uint8_t *m, const uint32_t *r1, const uint32_t *r2,
+                      const uint32_t *e, uint64_t *u_out, uint64_t *v_out, size_t count) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count == 0) return HQC_OK;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  hqc_sizes_t sz;
+  hqc_sizes(params->param_id, &sz);
+  const size_t c = count, uw = (size_t)si.u_words * 8, vw = (size_t)si.v_words * 8;
+  if (!aligned(h, 8) || !aligned(s, 8) || !aligned(u_out, 8) || !aligned(v_out, 8) ||
+      !aligned(r1, 4) || !aligned(r2, 4) || !aligned(e, 4))
+    return HQC_EINVAL;
+  if (!in_device_allocation(h, c * uw) || !in_device_allocation(s, c * uw) ||
+      !in_device_allocation(u_out, c * uw) || !in_device_allocation(v_out, c * vw) ||
+      !in_device_allocation(m, c * (size_t)si.k) ||
+      !in_device_allocation(r1, c * (size_t)sz.wr * 4) ||
+      !in_device_allocation(r2, c * (size_t)sz.wr * 4) ||
+      !in_device_allocation(e, c * (size_t)sz.we * 4))
+    return HQC_EINVAL;
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.h = h;
+  a.s = s;
+  a.m = m;
+  a.r1 = r1;
+  a.r2 = r2;
+  a.e = e;
+  a.u_out = u_out;
+  a.v_out = v_out;
+  a.count = (uint32_t)count;
+  return run_encrypt(true, params, a);
+}
+
 const char *hqc_strerror(int code) {
   switch (code) {
     case HQC_OK: return "success";

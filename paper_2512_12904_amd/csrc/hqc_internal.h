@@ -42,6 +42,20 @@ struct SetInfo {
 };
 
 bool set_info(int pid, SetInfo *out);
+
+// Key generation (s = x + h*y) and encryption (u, v from h, s, m, r1, r2, e),
+// one item per workgroup; per-item rows of every array.
+struct EncArgs {
+  const uint64_t *h, *s;
+  const uint32_t *x, *y;
+  const uint8_t *m;
+  const uint32_t *r1, *r2, *e;
+  uint64_t *s_out, *u_out, *v_out;
+  uint32_t count;
+};
+const void *encrypt_kernel_ptr(bool encrypt, int pid);
+size_t encrypt_lds_bytes(int pid);
+hipError_t launch_encrypt(bool encrypt, int pid, const EncArgs &a, int grid, hipStream_t stream);
 // mask: bit 0 = HQC-1, bit 1 = HQC-3, bit 2 = HQC-5 present in the launch.
 const void *kernel_ptr(int op, unsigned mask);
 size_t lds_bytes_for(unsigned mask);

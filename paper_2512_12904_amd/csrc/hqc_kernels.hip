@@ -30,139 +30,10 @@
 // Constant time: loop bounds and branches depend only on the parameter set,
 // the tile size and loop counters; secret values flow only through selects,
 // funnel-shift amounts, uniform LDS window offsets and bpermute indices.
-#include "hqc_internal.h"
+#include "hqc_device.h"
 
 namespace hqc {
 namespace {
-
-// ---- parameter sets (Table I) --------------------------------------------
-template <int ID> struct Set;
-template <> struct Set<1> { static constexpr int n = 17669, n1 = 46, n2 = 384, k = 16, delta = 15, w = 66; };
-template <> struct Set<3> { static constexpr int n = 35851, n1 = 56, n2 = 640, k = 24, delta = 16, w = 100; };
-template <> struct Set<5> { static constexpr int n = 57637, n1 = 90, n2 = 640, k = 32, delta = 29, w = 131; };
-
-// smallest multiple of 4 bytes >= b whose dword count is odd (so that 64
-// lanes reading the same offset of their own rows hit distinct banks)
-constexpr int odd_dword_stride(int b) {
-  int d = (b + 3) / 4;
-  return 4 * (d | 1);
-}
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
-template <int ID> struct Geo {
-  using S = Set<ID>;
-  static constexpr int n = S::n, n1 = S::n1, n2 = S::n2, k = S::k, w = S::w;
-  static constexpr int MULT = n2 / 128;
-  static constexpr int TD = 2 * S::delta;            // number of syndromes
-  static constexpr int W32 = n1 * n2 / 32;           // dwords of v and of the product we keep
-  static constexpr int R = ((W32 + 63) / 64) | 1;    // product dwords per lane (odd)
-  static constexpr int DW = n / 32;                  // dword holding bit n - 1
-  static constexpr int NB = n % 32;                  // bits of u in that dword
-  static constexpr int U_WORDS = (n + 63) / 64;
-  static constexpr int V_WORDS = n1 * n2 / 64;
-  static constexpr int BLK = 4 * MULT;               // dwords per RM block
-  static constexpr int BSTR = BLK + 1;               // padded LDS row of a block
-  static constexpr int U2 = 64 * R + DW + 2;         // doubled-u dwords (covers every window)
-  static constexpr int RB = n1 * BSTR;               // received-word dwords
-  static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
-  static constexpr int SYMREG = (n1 + 63) / 64;      // blocks per lane
-  // Reed-Solomon scratch per lane (uint16 entries): reversed log-syndromes
-  // (2 TD entries, zero-padded) then the error evaluator's logs (TD entries)
-  static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 3 * TD);
-  static constexpr int RS_STR = RS_BYTES_LANE / 2;   // in uint16 entries
-  static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
-  static constexpr int A_BYTES = (cmax(4 * (U2 + RB), 64 * RS_BYTES_LANE) + 15) / 16 * 16;
-  static constexpr int LDS_BYTES = A_BYTES + 64 * SSTR;
-  static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
-  static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");
-  static_assert(n1 * n2 % 64 == 0, "v is a whole number of words");
-  static_assert(64 * R >= W32, "lanes cover the product");
-  static_assert(TD + k == n1 && n1 < 255, "message positions");
-};
-
-// ---- GF(2^8) tables, x^8 + x^4 + x^3 + x^2 + 1, alpha = x ------------------
-struct GfTables {
-  uint32_t exp4[64];  // bytes exp[4l .. 4l+3]; exp[255] = exp[0] = 1
-  uint32_t log4[64];  // bytes log[4l .. 4l+3]; log[0] = 0 (callers mark zero)
-};
-
-constexpr GfTables make_gf_tables() {
-  GfTables t{};
-  uint8_t e[256] = {}, l[256] = {};
-  unsigned x = 1;
-  for (int i = 0; i < 255; ++i) {
-    e[i] = (uint8_t)x;
-    l[x] = (uint8_t)i;
-    x <<= 1;
-    if (x & 0x100u) x ^= 0x11Du;
-  }
-  e[255] = 1;
-  for (int i = 0; i < 64; ++i) {
-    t.exp4[i] = (uint32_t)e[4 * i] | (uint32_t)e[4 * i + 1] << 8 | (uint32_t)e[4 * i + 2] << 16 |
-                (uint32_t)e[4 * i + 3] << 24;
-    t.log4[i] = (uint32_t)l[4 * i] | (uint32_t)l[4 * i + 1] << 8 | (uint32_t)l[4 * i + 2] << 16 |
-                (uint32_t)l[4 * i + 3] << 24;
-  }
-  return t;
-}
-
-__constant__ GfTables kGf = make_gf_tables();
-
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-// A log value >= ZL stands for the log of zero; sums of two logs and one
-// reduction step keep it >= 512.
-constexpr uint32_t ZL = 0x400;
-
-__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
-
-// The workgroup is one wavefront and a wavefront's LDS operations complete in
-// issue order, so ordering LDS traffic between lanes needs no s_barrier; the
-// wavefront-scope fences only stop the compiler from moving memory
-// operations across this point.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Byte idx (0..255) of a table spread over the wave, 4 bytes per lane, read
-// through the LDS crossbar (ds_bpermute_b32 selects lane idx >> 2).  Must run
-// with all 64 lanes active.  width 8 returns the byte, width 0 returns 0.
-__device__ __forceinline__ uint32_t tab(uint32_t table4, uint32_t idx, uint32_t width = 8) {
-  uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)idx, (int)table4);
-  return __builtin_amdgcn_ubfe(w, idx << 3, width);
-}
-
-// s mod 255 for s in [0, 509] (as an exp index in [0, 254])
-__device__ __forceinline__ uint32_t red255(uint32_t s) {
-  uint32_t t = s - 255u;
-  return t < s ? t : s;  // unsigned: t wraps above s when s < 255
-}
-
-// log with zero marked: log(x), or ZL (+ log[0]) when x == 0
-__device__ __forceinline__ uint32_t logz(uint32_t log4, uint32_t x) {
-  return tab(log4, x) | (x == 0 ? ZL : 0u);
-}
-
-// alpha^s for a sum of logs s (0 when s carries a zero mark)
-__device__ __forceinline__ uint32_t expz(uint32_t exp4, uint32_t s) {
-  uint32_t v = tab(exp4, red255(s) & 0xFFu);
-  return s < 512u ? v : 0u;
-}
-
-// three-input bitwise functions (v_bitop3_b32, truth table over the inputs)
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
-}
-
-__device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
 
 // ---- S3-S5: one duplicated RM(1,7) block -> symbol byte ---------------------
 template <int MULT>
@@ -323,67 +194,15 @@ __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *l
     const int d = lane + 64 * i;
     if (d <= G::DW) u2[d] = r.u[i];
   }
-  // per index: sh = n - (y mod n) in [1, n]; window dword offset sh >> 5,
-  // funnel-shift amount sh & 31 (v_alignbit_b32 reads the low 5 bits)
   uint32_t shreg[G::YREG];
-#pragma unroll
-  for (int c = 0; c < G::YREG; ++c) shreg[c] = (uint32_t)G::n - r.y[c] % (uint32_t)G::n;
-  wave_sync();
-  const uint32_t udw = u2[G::DW] & ((1u << G::NB) - 1u);
-  const uint32_t u0 = u2[0];
-  wave_sync();
-  for (int D = G::DW + lane; D < G::U2; D += 64) {
-    const int i = D - G::DW;  // >= 0
-    uint32_t val;
-    if (i == 0) {
-      val = udw | (u0 << G::NB);
-    } else {
-      const int ih = i < G::DW ? i : G::DW - 1, il = i - 1 < G::DW ? i - 1 : G::DW - 1;
-      uint32_t hi = i < G::DW ? u2[ih] : (i == G::DW ? udw : 0u);
-      uint32_t lo = i - 1 < G::DW ? u2[il] : (i - 1 == G::DW ? udw : 0u);
-      val = __builtin_amdgcn_alignbit(hi, lo, 32 - G::NB);
-    }
-    u2[D] = val;
-  }
-  wave_sync();
+  window_shifts<ID, G::YREG>(r.y, shreg);
+  build_doubled<ID>(u2);
 
-  // S1: product, R output dwords per lane.  The windows of U consecutive
-  // indices are loaded together, then combined in order, so the later loads
-  // overlap the funnel shifts of the earlier ones.
+  // S1: product, R output dwords per lane
   uint32_t acc[G::R];
 #pragma unroll
   for (int j = 0; j < G::R; ++j) acc[j] = 0;
-  const uint32_t *base = u2 + lane * G::R;
-  constexpr int U = G::R <= 10 ? 4 : 2;
-#pragma unroll
-  for (int c = 0; c < G::YREG; ++c) {
-    const int cnt = (G::w - 64 * c) < 64 ? (G::w - 64 * c) : 64;
-    int kk = 0;
-    for (; kk + U <= cnt; kk += U) {
-      uint32_t win[U][G::R + 1], shs[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        shs[q] = rdlane(shreg[c], kk + q);
-#pragma unroll
-        for (int j = 0; j <= G::R; ++j) win[q][j] = base[(shs[q] >> 5) + j];
-      }
-      // two indices per three-way XOR
-#pragma unroll
-      for (int q = 0; q < U; q += 2)
-#pragma unroll
-        for (int j = 0; j < G::R; ++j)
-          acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
-                        __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
-    }
-    for (; kk < cnt; ++kk) {
-      uint32_t win[G::R + 1];
-      const uint32_t sh = rdlane(shreg[c], kk);
-#pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[j] = base[(sh >> 5) + j];
-#pragma unroll
-      for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
-    }
-  }
+  product_acc<ID, G::w>(u2, shreg, acc);
   // S2: r = v + (u*y) restricted to the first n1*n2 bits
 #pragma unroll
   for (int j = 0; j < G::R; ++j) {

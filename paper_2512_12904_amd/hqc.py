@@ -28,7 +28,8 @@ EXPORTS = (
     "hqc_sizes", "hqc_decrypt_batch", "hqc_decode_batch", "hqc_decrypt_mixed",
     "hqc_decode_mixed", "hqc_keystore_create", "hqc_keystore_put", "hqc_keystore_put_many",
     "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
-    "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown",
+    "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
+    "hqc_encrypt_batch",
 )
 
 
@@ -85,6 +86,8 @@ def lib():
         L.hqc_strerror.argtypes = [ctypes.c_int]
         L.hqc_last_hip_error.argtypes = []
         L.hqc_default_grid.argtypes = [ctypes.c_int]
+        L.hqc_keygen_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, sz]
+        L.hqc_encrypt_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp, sz]
         L.hqc_shutdown.restype = None
         L.hqc_shutdown.argtypes = []
         _lib = L
@@ -252,6 +255,44 @@ def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, strea
         _dev(out, torch.uint8, "out", (count, s["k"])), count)
     _check(rc, "hqc_decrypt_batch_keyed")
     return out
+
+
+def keygen_batch(pid, h, x, y, out=None, grid=0, stream=None):
+    """s[i] = x[i] + h[i]*y[i] (Alg. 3; the randomness h, x, y is an input)."""
+    sz = sizes(pid)
+    count = h.shape[0]
+    if out is None:
+        out = torch.empty((count, sz["u_words"]), dtype=torch.int64, device=h.device)
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_keygen_batch(
+        ctypes.byref(p), _dev(h, torch.int64, "h", (count, sz["u_words"])),
+        _dev(x, torch.int32, "x", (count, sz["w"])), _dev(y, torch.int32, "y", (count, sz["w"])),
+        _dev(out, torch.int64, "out", (count, sz["u_words"])), count)
+    _check(rc, "hqc_keygen_batch")
+    return out
+
+
+def encrypt_batch(pid, h, s, m, r1, r2, e, u_out=None, v_out=None, grid=0, stream=None):
+    """(u, v) = HQC.PKE.Encrypt((h[i], s[i]), m[i]) with the randomness
+    r1, r2, e as input (Alg. 1)."""
+    sz = sizes(pid)
+    count = h.shape[0]
+    dev = h.device
+    if u_out is None:
+        u_out = torch.empty((count, sz["u_words"]), dtype=torch.int64, device=dev)
+    if v_out is None:
+        v_out = torch.empty((count, sz["v_words"]), dtype=torch.int64, device=dev)
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_encrypt_batch(
+        ctypes.byref(p), _dev(h, torch.int64, "h", (count, sz["u_words"])),
+        _dev(s, torch.int64, "s", (count, sz["u_words"])),
+        _dev(m, torch.uint8, "m", (count, sz["k"])),
+        _dev(r1, torch.int32, "r1", (count, sz["wr"])), _dev(r2, torch.int32, "r2", (count, sz["wr"])),
+        _dev(e, torch.int32, "e", (count, sz["we"])),
+        _dev(u_out, torch.int64, "u_out", (count, sz["u_words"])),
+        _dev(v_out, torch.int64, "v_out", (count, sz["v_words"])), count)
+    _check(rc, "hqc_encrypt_batch")
+    return u_out, v_out
 
 
 def default_grid(pid):
