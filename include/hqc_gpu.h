@@ -34,7 +34,8 @@
  * CUDA/HIP tensor), except y_host in hqc_keystore_put* and the hqc_params_t /
  * hqc_segment_t structs themselves, which are host memory read during the
  * call and not retained.  The caller owns all buffers.  u, v, r must be
- * 8-byte aligned, y and key_ids 4-byte aligned.
+ * 8-byte aligned, y, key_ids and m_out 4-byte aligned (m_out is written a
+ * dword at a time).
  *
  * Execution: calls enqueue work on params->stream (a hipStream_t; NULL means
  * the null stream) and return; outputs are valid once that stream is

@@ -222,7 +222,7 @@ int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::S
   o->count = (uint32_t)s.count;
   if (s.count == 0) return HQC_OK;
   const size_t c = s.count;
-  if (!s.u || !s.m_out || !aligned(s.u, 8)) return HQC_EINVAL;
+  if (!s.u || !s.m_out || !aligned(s.u, 8) || !aligned(s.m_out, 4)) return HQC_EINVAL;
   if (op == hqc::OP_DECODE) {
     if (!in_device_allocation(s.u, c * si.v_words * 8)) return HQC_EINVAL;
   } else {

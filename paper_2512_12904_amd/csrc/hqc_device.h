@@ -139,6 +139,16 @@ __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
+// v_permlane32_swap_b32 on two copies of x: .lo is lane (l mod 32)'s x and
+// .hi is lane (l mod 32) + 32's x, in every lane l
+struct Halves {
+  uint32_t lo, hi;
+};
+__device__ __forceinline__ Halves halves(uint32_t x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return {r[0], r[1]};
+}
+
 
 // ---- S0 / S1 building blocks -------------------------------------------------
 

@@ -320,8 +320,10 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
     my[2 * TD + e] = (uint16_t)logz(log4, om);
   }
 
-  // S8-S10: Chien + Forney at message position j = TD + t, then m_t
+  // S8-S10: Chien + Forney at message position j = TD + t, then m_t (four
+  // bytes of m to a dword store)
   const uint16_t *lom = my + 2 * TD;
+  uint32_t pack = 0;
 #pragma unroll 1
   for (int t = 0; t < G::k; ++t) {
     const uint32_t j = (uint32_t)(TD + t);
@@ -339,8 +341,157 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
     const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
     uint32_t e = tab(exp4, red255(x + 255u - j));
     e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
-    uint32_t mb = (cs[j] ^ e) & 0xFFu;
-    if (active) sg.m[(size_t)item * G::k + t] = (uint8_t)mb;
+    pack |= ((cs[j] ^ e) & 0xFFu) << (8 * (t & 3));
+    if ((t & 3) == 3) {
+      if (active) ((uint32_t *)(sg.m + (size_t)item * G::k))[t >> 2] = pack;
+      pack = 0;
+    }
+  }
+}
+
+// ---- S6-S10 with two lanes per item (tiles of at most 32 items) ---------------
+// Lanes l and l + 32 decode the same word.  Half h = l / 32 computes the
+// syndromes S_{hH+1} .. S_{hH+H} (H = delta) and holds the coefficients
+// 2i + h of Lambda and of B'; a discrepancy, an evaluator coefficient or a
+// value of Lambda / Omega is the XOR of the two halves' partial sums, and
+// the shift x * B' crosses between the halves, both through
+// v_permlane32_swap_b32.  The pair shares one LDS row `my`.
+template <int ID, int OP>
+__device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool active,
+                                        const uint8_t *cs, uint16_t *my, uint32_t exp4,
+                                        uint32_t log4) {
+  using G = Geo<ID>;
+  constexpr int TD = G::TD;
+  constexpr int H = TD / 2;
+  const bool hi = lane_id() >= 32;
+  const uint32_t h = hi ? 1u : 0u;
+
+  // S6: this half's H syndromes, in groups of SG
+  {
+    constexpr int SG = H <= 16 ? H : 10;
+    const uint32_t base = hi ? (uint32_t)H : 0u;
+    uint16_t *dst = my + (TD - 1) - (int)base;  // dst[-i] = my[TD - (base + i + 1)]
+#pragma unroll
+    for (int g0 = 0; g0 < H; g0 += SG) {
+      const int gn = H - g0 < SG ? H - g0 : SG;
+      const uint32_t step = base + (uint32_t)g0;
+      uint32_t acc[SG];
+#pragma unroll
+      for (int i = 0; i < SG; ++i) acc[i] = 0;
+      uint32_t gj = 0;  // (step * j) mod 255
+#pragma unroll 1
+      for (int j = 0; j < G::n1; ++j) {
+        const uint32_t c = cs[j];
+        const uint32_t width = c ? 8u : 0u;
+        uint32_t e = red255(tab(log4, c) + gj);
+#pragma unroll
+        for (int i = 0; i < SG; ++i) {
+          if (i < gn) {
+            e = red255(e + (uint32_t)j);
+            acc[i] ^= tab(exp4, e, width);
+          }
+        }
+        gj = red255(gj + step);
+      }
+#pragma unroll
+      for (int i = 0; i < SG; ++i)
+        if (i < gn) dst[-(g0 + i)] = (uint16_t)logz(log4, acc[i]);
+      wave_sync();
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) my[TD + (int)base + i] = (uint16_t)ZL;
+    wave_sync();
+  }
+
+  // S7: Berlekamp-Massey on interleaved halves; register i holds coefficient
+  // 2i + h (coefficient TD + 1 of the upper half stays zero)
+  uint32_t lam[H + 1], lb[H + 1], llk[H + 1];
+#pragma unroll
+  for (int i = 0; i <= H; ++i) {
+    lam[i] = (i == 0 && !hi) ? 1u : 0u;
+    lb[i] = (i == 0 && hi) ? 0u : ZL;
+    llk[i] = ZL;
+  }
+  uint32_t L = 0;
+#pragma unroll 1
+  for (int r = 1; r <= TD; ++r) {
+    const uint16_t *sp = my + (TD - r) + (int)h;  // sp[2i] = log S_{r - 2i - h}
+    uint32_t delta = 0;
+#pragma unroll
+    for (int i = 0; i <= H; ++i) {
+      if (2 * i < r) {
+        const uint32_t li = logz(log4, lam[i]);
+        llk[i] = li;
+        delta ^= expz(exp4, li + sp[2 * i]);
+      }
+    }
+    {
+      const Halves dv = halves(delta);
+      delta = dv.lo ^ dv.hi;
+    }
+    const uint32_t lD = logz(log4, delta);
+    const bool swap = delta != 0 && 2 * L <= (uint32_t)(r - 1);
+    const uint32_t nlD = 255u - (lD & 0xFFu);
+    uint32_t prev = ZL;  // B'_new[0]
+#pragma unroll
+    for (int i = 0; i <= H; ++i) {
+      if (2 * i <= r + 1) {
+        // what coefficient t = 2i + h passes on to B'_new[t + 1]
+        const uint32_t t = 2u * (uint32_t)i + h;
+        const uint32_t q = t < (uint32_t)r ? red255(llk[i] + nlD) : ZL;
+        const uint32_t src = swap ? q : lb[i];
+        lam[i] ^= expz(exp4, lD + lb[i]);
+        const Halves sv = halves(src);
+        lb[i] = hi ? sv.lo : prev;
+        prev = sv.hi;
+      }
+    }
+    L = swap ? (uint32_t)r - L : L;
+  }
+  uint32_t ll[H + 1];
+#pragma unroll
+  for (int i = 0; i <= H; ++i) ll[i] = logz(log4, lam[i]);
+
+  // S9 (part): Omega_e = sum_{i <= e} Lambda_i S_{e+1-i}; both halves store
+  // the same value
+#pragma unroll 1
+  for (int e = 0; e < TD; ++e) {
+    const uint16_t *sp = my + (TD - e - 1) + (int)h;  // sp[2i] = log S_{e+1-2i-h}
+    uint32_t om = 0;
+#pragma unroll
+    for (int i = 0; i <= H; ++i)
+      if (2 * i <= e) om ^= expz(exp4, ll[i] + sp[2 * i]);
+    const Halves ov = halves(om);
+    my[2 * TD + e] = (uint16_t)logz(log4, ov.lo ^ ov.hi);
+  }
+  wave_sync();
+
+  // S8-S10: each half evaluates its own coefficients (all odd ones are in
+  // the upper half, so its partial sum of Lambda is the odd part)
+  const uint16_t *lom = my + 2 * TD + (int)h;  // lom[2i] = log Omega_{2i+h}
+  uint32_t pack = 0;
+#pragma unroll 1
+  for (int t = 0; t < G::k; ++t) {
+    const uint32_t j = (uint32_t)(TD + t);
+    const uint32_t stp = 255u - 2u * j;         // -2j mod 255
+    uint32_t ex = hi ? 255u - j : 0u;            // -(2i + h) j mod 255
+    uint32_t lamp = 0, omp = 0;
+#pragma unroll
+    for (int i = 0; i <= H; ++i) {
+      if (i > 0) ex = red255(ex + stp);
+      lamp ^= expz(exp4, ll[i] + ex);
+      if (i < H) omp ^= expz(exp4, lom[2 * i] + ex);
+    }
+    const Halves lv = halves(lamp), wv = halves(omp);
+    const uint32_t lamv = lv.lo ^ lv.hi, oddv = lv.hi, omv = wv.lo ^ wv.hi;
+    const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
+    uint32_t e = tab(exp4, red255(x + 255u - j));
+    e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
+    pack |= ((cs[j] ^ e) & 0xFFu) << (8 * (t & 3));
+    if ((t & 3) == 3) {
+      if (active && !hi) ((uint32_t *)(sg.m + (size_t)item * G::k))[t >> 2] = pack;
+      pack = 0;
+    }
   }
 }
 
@@ -366,19 +517,25 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
     }
     wave_sync();
   }
-  // one Reed-Solomon word per lane; lanes past the tile decode a copy of its
-  // first item and store nothing
-  const int slot = lane < nt ? lane : 0;
+  // one Reed-Solomon word per lane, or per pair of lanes l, l + 32 when the
+  // tile has at most 32 items; lanes past the tile decode a copy of its first
+  // item and store nothing
+  const bool pair = nt <= 32;
+  const int s = pair ? (lane & 31) : lane;
+  const int slot = s < nt ? s : 0;
   const uint32_t item = item0 + (uint32_t)slot;
-  bool active = lane < nt;
+  bool active = s < nt;
   bool bad_key = false;
   if constexpr (OP == OP_KEYED) {
     bad_key = sg.key_ids[item] >= sg.ks_cap;
   }
-  uint16_t *my = (uint16_t *)lds + lane * G::RS_STR;
-  rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+  uint16_t *my = (uint16_t *)lds + s * G::RS_STR;
+  if (pair)
+    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+  else
+    rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
   if constexpr (OP == OP_KEYED) {
-    if (active && bad_key) {
+    if (active && bad_key && s == lane) {
       for (int t = 0; t < G::k; ++t) sg.m[(size_t)item * G::k + t] = 0;
       atomicAdd(sg.ks_bad, 1ull);
     }

@@ -69,8 +69,9 @@ def test_invalid_arguments_rejected_before_launch(gpu_lib):
     # NULL buffers with count > 0
     assert L.hqc_decrypt_batch(ctypes.byref(p), None, vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
     assert L.hqc_decode_batch(ctypes.byref(p), None, vp(8), 1) == gpu_lib.HQC_EINVAL
-    # misaligned u
+    # misaligned u, misaligned m_out
     assert L.hqc_decrypt_batch(ctypes.byref(p), vp(12), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    assert L.hqc_decode_batch(ctypes.byref(p), vp(8), vp(10), 1) == gpu_lib.HQC_EINVAL
     # oversize count
     assert L.hqc_decode_batch(ctypes.byref(p), vp(8), vp(8), 1 << 40) == gpu_lib.HQC_ERANGE
     # count == 0 is a no-op, whatever the pointers

@@ -121,6 +121,22 @@ def test_decode_random_words_match_oracle(hqc, pid):
     assert (got == oracle.decode_batch(pid, r)).all()
 
 
+@pytest.mark.parametrize("pid", [1, 3, 5])
+@pytest.mark.parametrize("tile", [1, 31, 32, 33, 64])
+def test_tile_sizes(hqc, pid, tile):
+    # tiles of at most 32 items decode each Reed-Solomon word on a pair of
+    # lanes, larger ones on one lane; 200 = 6 * 33 + 2 also leaves a ragged
+    # last tile
+    say("case: pid=%d tile=%d grid=3" % (pid, tile))
+    d = datasets.stress(pid, 200, 0x600 + tile)
+    got = host(hqc.decode_batch(pid, dev(d["r"]), grid=3, tile=tile))
+    assert (got == d["m"]).all()
+    p = datasets.sizes(pid)
+    r = synth.words(0x700 + tile + pid, (70, p["vwords"]))
+    got = host(hqc.decode_batch(pid, dev(r), grid=3, tile=tile))
+    assert (got == oracle.decode_batch(pid, r)).all()
+
+
 def test_mixed_launch_equals_separate(hqc):
     say("case: mixed decrypt + decode")
     ds = {pid: datasets.pke(pid, 50 + pid, 0x300 + pid) for pid in (5, 1, 3)}
@@ -145,17 +161,18 @@ def test_per_item_and_graph_modes(hqc):
         assert (host(out) == d["m"]).all()
 
 
-def test_keystore(hqc):
-    say("case: keystore")
+@pytest.mark.parametrize("tile", [0, 64])
+def test_keystore(hqc, tile):
+    say("case: keystore tile=%d" % tile)
     import torch
     d = datasets.pke(1, 40, 0x500)
     ks = hqc.KeyStore(40, 1, 1)
     ks.put(1, 0, d["y_keys"])
     ids = torch.arange(40, dtype=torch.int32, device="cuda")
-    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids))
+    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids, tile=tile))
     assert (got == d["m"]).all()
     ids[5] = 1000  # out of range: zeros, counted
-    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids))
+    got = host(hqc.decrypt_batch_keyed(1, ks, dev(d["u"]), dev(d["v"]), ids, tile=tile))
     assert (got[5] == 0).all() and (np.delete(got, 5, 0) == np.delete(d["m"], 5, 0)).all()
     assert ks.bad_ids() == 1
     with pytest.raises(hqc.HqcError):
