@@ -46,8 +46,16 @@ template <int ID> struct Geo {
   static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 3 * TD);
   static constexpr int RS_STR = RS_BYTES_LANE / 2;   // in uint16 entries
   static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
-  static constexpr int A_BYTES = (cmax(4 * (U2 + RB), 64 * RS_BYTES_LANE) + 15) / 16 * 16;
-  static constexpr int LDS_BYTES = A_BYTES + 64 * SSTR;
+  // HQC-5 runs a tile as sub-tiles of at most 32 items (two lanes per
+  // Reed-Solomon word) and builds the received word over the doubled u once
+  // the product is in registers, so that one wavefront fits in 20 KiB of LDS
+  // (eight wavefronts per CU)
+  static constexpr bool COMPACT = ID == 5;
+  static constexpr int TROWS = COMPACT ? 32 : 64;    // items per (sub-)tile
+  static constexpr int RB_OFF = COMPACT ? 0 : U2;    // dword offset of the received word
+  static constexpr int A_BYTES =
+      (cmax(4 * (COMPACT ? cmax(U2, RB) : U2 + RB), TROWS * RS_BYTES_LANE) + 15) / 16 * 16;
+  static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
   static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
   static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");
   static_assert(n1 * n2 % 64 == 0, "v is a whole number of words");

@@ -145,10 +145,12 @@ __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRe
   const int lane = lane_id();
   const uint32_t *vsrc = (const uint32_t *)((OP == OP_DECODE ? sg.u : sg.v) +
                                             (size_t)item * G::V_WORDS);
+  if (!G::COMPACT || OP == OP_DECODE) {  // the compact layout reads v after the product
 #pragma unroll
-  for (int i = 0; i < IR::VREG; ++i) {
-    const int d = lane + 64 * i;
-    r.v[i] = d < G::W32 ? vsrc[d] : 0u;
+    for (int i = 0; i < IR::VREG; ++i) {
+      const int d = lane + 64 * i;
+      r.v[i] = d < G::W32 ? vsrc[d] : 0u;
+    }
   }
   if constexpr (OP != OP_DECODE) {
     const uint32_t *usrc = (const uint32_t *)(sg.u + (size_t)item * G::U_WORDS);
@@ -173,17 +175,20 @@ __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRe
 }
 
 template <int ID, int OP>
-__device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *lds) {
+__device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *lds,
+                                              const uint32_t *vsrc) {
   using G = Geo<ID>;
   using IR = ItemRegs<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
-  uint32_t *rb = lds + G::U2;
+  uint32_t *rb = lds + G::RB_OFF;
 
+  if (!G::COMPACT || OP == OP_DECODE) {
 #pragma unroll
-  for (int i = 0; i < IR::VREG; ++i) {
-    const int d = lane + 64 * i;
-    if (d < G::W32) rb[d + d / G::BLK] = r.v[i];
+    for (int i = 0; i < IR::VREG; ++i) {
+      const int d = lane + 64 * i;
+      if (d < G::W32) rb[d + d / G::BLK] = r.v[i];
+    }
   }
   if constexpr (OP == OP_DECODE) return;
 
@@ -204,10 +209,25 @@ __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *l
   for (int j = 0; j < G::R; ++j) acc[j] = 0;
   product_acc<ID, G::w>(u2, shreg, acc);
   // S2: r = v + (u*y) restricted to the first n1*n2 bits
+  if constexpr (G::COMPACT) {
+    wave_sync();  // every window of U2 has been read: the rows take its place
 #pragma unroll
-  for (int j = 0; j < G::R; ++j) {
-    const int d = lane * G::R + j;
-    if (d < G::W32) rb[d + d / G::BLK] ^= acc[j];
+    for (int j = 0; j < G::R; ++j) {
+      const int d = lane * G::R + j;
+      if (d < G::W32) rb[d + d / G::BLK] = acc[j];
+    }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < IR::VREG; ++i) {
+      const int d = lane + 64 * i;
+      if (d < G::W32) rb[d + d / G::BLK] ^= vsrc[d];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) {
+      const int d = lane * G::R + j;
+      if (d < G::W32) rb[d + d / G::BLK] ^= acc[j];
+    }
   }
 }
 
@@ -496,18 +516,23 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
 }
 
 template <int ID, int OP>
-__device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
-                                         uint32_t exp4, uint32_t log4) {
+__device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
+                                        uint32_t exp4, uint32_t log4) {
   using G = Geo<ID>;
   const int lane = lane_id();
   uint8_t *sym = (uint8_t *)lds + G::A_BYTES;
+  // the next item's u, v and y are loaded into VGPRs while this one's RM
+  // blocks decode; the compact layout (HQC-5) loads each item when it starts,
+  // leaving the latency to the other wavefronts on the SIMD
   ItemRegs<ID> regs;
-  prefetch<ID, OP>(sg, item0, regs);
+  if constexpr (!G::COMPACT) prefetch<ID, OP>(sg, item0, regs);
   for (int it = 0; it < nt; ++it) {
-    received_word<ID, OP>(regs, lds);
+    const uint32_t cur = item0 + (uint32_t)it;
+    if constexpr (G::COMPACT) prefetch<ID, OP>(sg, cur, regs);
+    received_word<ID, OP>(regs, lds, (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS));
     wave_sync();
-    if (it + 1 < nt) prefetch<ID, OP>(sg, item0 + (uint32_t)it + 1, regs);
-    const uint32_t *rb = lds + G::U2;
+    if (!G::COMPACT && it + 1 < nt) prefetch<ID, OP>(sg, cur + 1, regs);
+    const uint32_t *rb = lds + G::RB_OFF;
 #pragma unroll
     for (int pass = 0; pass < G::SYMREG; ++pass) {
       const int j = lane + 64 * pass;
@@ -520,7 +545,7 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
   // one Reed-Solomon word per lane, or per pair of lanes l, l + 32 when the
   // tile has at most 32 items; lanes past the tile decode a copy of its first
   // item and store nothing
-  const bool pair = nt <= 32;
+  const bool pair = G::COMPACT || nt <= 32;
   const int s = pair ? (lane & 31) : lane;
   const int slot = s < nt ? s : 0;
   const uint32_t item = item0 + (uint32_t)slot;
@@ -530,10 +555,14 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
     bad_key = sg.key_ids[item] >= sg.ks_cap;
   }
   uint16_t *my = (uint16_t *)lds + s * G::RS_STR;
-  if (pair)
+  if constexpr (G::COMPACT) {
     rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
-  else
-    rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+  } else {
+    if (pair)
+      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+    else
+      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+  }
   if constexpr (OP == OP_KEYED) {
     if (active && bad_key && s == lane) {
       for (int t = 0; t < G::k; ++t) sg.m[(size_t)item * G::k + t] = 0;
@@ -541,6 +570,20 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
     }
   }
   wave_sync();
+}
+
+// a tile of nt <= 64 items; HQC-5 takes it 32 items at a time
+template <int ID, int OP>
+__device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
+                                         uint32_t exp4, uint32_t log4) {
+  using G = Geo<ID>;
+  if constexpr (G::COMPACT) {
+    for (int s0 = 0; s0 < nt; s0 += G::TROWS)
+      run_sub<ID, OP>(sg, item0 + (uint32_t)s0, nt - s0 < G::TROWS ? nt - s0 : G::TROWS, lds,
+                      exp4, log4);
+  } else {
+    run_sub<ID, OP>(sg, item0, nt, lds, exp4, log4);
+  }
 }
 
 template <int OP, unsigned MASK>
