@@ -101,28 +101,27 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
   // H = transform of the counts.  The correlation with codeword (u, sign) is
   // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u) with H'(0) = H(0) - 64*MULT,
   // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
-  // Keys (16 bits): |H'| << 7 | (127 - u), |H'| <= 64*MULT <= 320.
+  // One 16-bit key per u: bits 15..8 = |H'(u)| (<= 192 for MULT 3) or
+  // |H'(u)| >> 1 (<= 160 for MULT 5; every H'(u) has the parity of sum F, so
+  // halving keeps the order), bits 7..1 = 127 - u, bit 0 = [H'(u) > 0].
   h[0].x = (short)(h[0].x - 64 * MULT);
   __builtin_amdgcn_sched_barrier(0);
-  u16x2 kpos = {0, 0}, kneg = {0, 0};
+  u16x2 kmax = {0, 0};
 #pragma unroll
   for (int m = 0; m < 64; ++m) {
     // dword m holds u = m (low half) and u = m + 64 (high half)
-    const u16x2 idx = {(unsigned short)(127 - m), (unsigned short)(63 - m)};
+    const uint32_t idx = (uint32_t)(127 - m) << 1 | (uint32_t)(63 - m) << 17;
     const s16x2 zero = {0, 0};
-    s16x2 pos = __builtin_elementwise_max(h[m], zero);
-    s16x2 neg = __builtin_elementwise_max(zero - h[m], zero);
-    u16x2 kp = __builtin_bit_cast(u16x2, pos) * (unsigned short)128 + idx;
-    u16x2 kn = __builtin_bit_cast(u16x2, neg) * (unsigned short)128 + idx;
-    kpos = __builtin_elementwise_max(kpos, kp);
-    kneg = __builtin_elementwise_max(kneg, kn);
+    const s16x2 neg = zero - h[m];
+    const s16x2 mag = __builtin_elementwise_max(h[m], neg);
+    const u16x2 sgn = __builtin_bit_cast(u16x2, neg) >> (unsigned short)15;  // [H' > 0]
+    const uint32_t mw = __builtin_bit_cast(uint32_t, mag);
+    const uint32_t hiw = MULT == 3 ? mw << 8 : (mw << 7) & 0xFF00FF00u;
+    const uint32_t key = hiw | __builtin_bit_cast(uint32_t, sgn) | idx;
+    kmax = __builtin_elementwise_max(kmax, __builtin_bit_cast(u16x2, key));
   }
-  uint32_t bp = kpos.x > kpos.y ? kpos.x : kpos.y;
-  uint32_t bn = kneg.x > kneg.y ? kneg.x : kneg.y;
-  // keys are distinct (the index is part of them) and the peak is nonzero
-  const bool positive = bp > bn;
-  const uint32_t best = positive ? bp : bn;
-  return (127u - (best & 127u)) | (positive ? 0x80u : 0u);
+  const uint32_t best = kmax.x > kmax.y ? kmax.x : kmax.y;
+  return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
 }
 
 // ---- S0-S2: received word r = v + (u*y)|_{n1 n2} into the padded rows -------
