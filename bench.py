@@ -113,13 +113,18 @@ def time_per_item(hqc, pid, u, v, y, out):
 GRID = 0  # launch knobs (0 = the library's choice); set from the command line
 TILE = 0
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_12904_amd", "csrc", "hqc_kernels.hip")
+# the sources the decryption kernel is compiled from
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12904_amd", "csrc", f)
+                  for f in ("hqc_kernels.hip", "hqc_device.h", "hqc_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hqc1_b65536.json")
 
 
 def kernel_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
