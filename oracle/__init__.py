@@ -12,6 +12,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hqc_oracle.c")
+_SOURCES = [_SRC, os.path.join(_HERE, "kem_oracle.c")]
+_HEADERS = [os.path.join(_HERE, "hqc_oracle.h"), os.path.join(_HERE, "kem_oracle.h")]
 _SO = os.path.join(_HERE, "libhqc_oracle.so")
 _lib = None
 
@@ -25,7 +27,7 @@ I64P = ctypes.POINTER(ctypes.c_int64)
 def build():
     """Compile the oracle with gcc into oracle/libhqc_oracle.so."""
     subprocess.check_call(["gcc", "-std=c11", "-O2", "-Wall", "-fPIC", "-shared",
-                           "-o", _SO, _SRC, "-lpthread"])
+                           "-o", _SO] + _SOURCES + ["-lpthread"])
 
 
 class _Param(ctypes.Structure):
@@ -43,7 +45,8 @@ class _Trace(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(f)
+                                          for f in _SOURCES + _HEADERS):
             build()
         L = ctypes.CDLL(_SO)
         L.hqco_param.argtypes = [ctypes.c_int, ctypes.POINTER(_Param)]
@@ -78,11 +81,23 @@ def lib():
                                          U32P, U32P, U32P, U64P, U64P, ctypes.c_int]
         L.hqco_decrypt_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U32P, I64P, U64P, U64P,
                                          U8P, ctypes.c_int]
+        L.hqco_keccak_f1600.argtypes = [U64P]
+        L.hqco_shake256.argtypes = [U8P, ctypes.c_size_t, U8P, ctypes.c_size_t]
+        L.hqco_fixed_weight.argtypes = [ctypes.c_int, ctypes.c_int, U32P, U32P]
+        L.hqco_kem_seed_words.argtypes = [ctypes.c_int, U8P, U32P]
+        L.hqco_kem_encaps.argtypes = [ctypes.c_int, U64P, U64P, U8P, U64P, U64P, U8P]
+        L.hqco_kem_decaps.restype = ctypes.c_int
+        L.hqco_kem_decaps.argtypes = [ctypes.c_int, U64P, U64P, U32P, U8P, U64P, U64P, U8P]
+        L.hqco_kem_encaps_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U64P, U64P, U8P,
+                                            U64P, U64P, U8P, ctypes.c_int]
+        L.hqco_kem_decaps_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U64P, U64P, U32P,
+                                            U8P, U64P, U64P, U8P, I32P, ctypes.c_int]
         L.hqco_decode_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U64P, U8P, ctypes.c_int]
         L.hqco_stress_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U8P, U32P, U8P, U64P,
                                         U64P, ctypes.c_int]
         for f in ("hqco_keygen_batch", "hqco_encrypt_batch", "hqco_decrypt_batch",
-                  "hqco_decode_batch", "hqco_stress_batch", "hqco_param"):
+                  "hqco_decode_batch", "hqco_stress_batch", "hqco_param",
+                  "hqco_kem_encaps_batch", "hqco_kem_decaps_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -329,3 +344,81 @@ def stress_batch(pid, m, bad, dval, noise, out=None, nthreads=None):
     _check(lib().hqco_stress_batch(pid, cnt, _p(m, U8P), _p(bad, U32P), _p(dval, U8P),
                                    _p(noise, U64P), _p(r, U64P), nthreads or default_threads()))
     return r
+
+
+# ---- KEM (kem_oracle.c) -------------------------------------------------------
+
+KEM_KEY_BYTES = 32
+
+
+def keccak_f1600(state):
+    a = _u64(state).copy()
+    assert a.shape == (25,)
+    lib().hqco_keccak_f1600(_p(a, U64P))
+    return a
+
+
+def shake256(data, outlen):
+    src = np.frombuffer(bytes(data) + b"\0", dtype=np.uint8).copy()
+    out = np.zeros(outlen + 1, np.uint8)
+    lib().hqco_shake256(_p(src, U8P), len(data), _p(out, U8P), outlen)
+    return bytes(out[:outlen])
+
+
+def fixed_weight(n, w, a):
+    a = _u32(a)
+    assert a.shape == (w,)
+    out = np.zeros(w, np.uint32)
+    lib().hqco_fixed_weight(n, w, _p(a, U32P), _p(out, U32P))
+    return out
+
+
+def kem_seed_words(pid, m):
+    p = param(pid)
+    m = _u8(m)
+    out = np.zeros(2 * p["wr"] + p["we"], np.uint32)
+    lib().hqco_kem_seed_words(pid, _p(m, U8P), _p(out, U32P))
+    return out
+
+
+def kem_encaps(pid, h, s, m):
+    p = param(pid)
+    h, s, m = _u64(h), _u64(s), _u8(m)
+    u = np.zeros(p["nwords"], np.uint64)
+    v = np.zeros(p["vwords"], np.uint64)
+    key = np.zeros(KEM_KEY_BYTES, np.uint8)
+    lib().hqco_kem_encaps(pid, _p(h, U64P), _p(s, U64P), _p(m, U8P), _p(u, U64P), _p(v, U64P),
+                          _p(key, U8P))
+    return u, v, key
+
+
+def kem_decaps(pid, h, s, y, sigma, u, v):
+    h, s, y, sigma, u, v = _u64(h), _u64(s), _u32(y), _u8(sigma), _u64(u), _u64(v)
+    key = np.zeros(KEM_KEY_BYTES, np.uint8)
+    ok = lib().hqco_kem_decaps(pid, _p(h, U64P), _p(s, U64P), _p(y, U32P), _p(sigma, U8P),
+                               _p(u, U64P), _p(v, U64P), _p(key, U8P))
+    return key, bool(ok)
+
+
+def kem_encaps_batch(pid, h, s, m, nthreads=None):
+    p = param(pid)
+    h, s, m = _u64(h), _u64(s), _u8(m)
+    count = m.shape[0]
+    u = np.zeros((count, p["nwords"]), np.uint64)
+    v = np.zeros((count, p["vwords"]), np.uint64)
+    key = np.zeros((count, KEM_KEY_BYTES), np.uint8)
+    _check(lib().hqco_kem_encaps_batch(pid, count, _p(h, U64P), _p(s, U64P), _p(m, U8P),
+                                       _p(u, U64P), _p(v, U64P), _p(key, U8P),
+                                       nthreads or default_threads()))
+    return u, v, key
+
+
+def kem_decaps_batch(pid, h, s, y, sigma, u, v, nthreads=None):
+    h, s, y, sigma, u, v = _u64(h), _u64(s), _u32(y), _u8(sigma), _u64(u), _u64(v)
+    count = u.shape[0]
+    key = np.zeros((count, KEM_KEY_BYTES), np.uint8)
+    ok = np.zeros(count, np.int32)
+    _check(lib().hqco_kem_decaps_batch(pid, count, _p(h, U64P), _p(s, U64P), _p(y, U32P),
+                                       _p(sigma, U8P), _p(u, U64P), _p(v, U64P), _p(key, U8P),
+                                       _p(ok, I32P), nthreads or default_threads()))
+    return key, ok.astype(bool)

@@ -23,7 +23,7 @@ def pke(pid, count, master, shared_key=False):
     m, r1, r2, e = synth.encryptions(master, pid, p, count, key_of=key_of)
     u, v = oracle.encrypt_batch(pid, h, s, m, r1, r2, e, key_of=key_of)
     y_items = y[key_of]
-    return {"pid": pid, "h": h, "y_keys": y, "key_of": key_of, "y": np.ascontiguousarray(y_items),
+    return {"pid": pid, "h": h, "s": s, "y_keys": y, "key_of": key_of, "y": np.ascontiguousarray(y_items),
             "m": m, "u": u, "v": v}
 
 
