@@ -170,6 +170,42 @@ int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint6
                       const uint8_t *m, const uint32_t *r1, const uint32_t *r2,
                       const uint32_t *e, uint64_t *u_out, uint64_t *v_out, size_t count);
 
+/* ---- KEM (Sec. II-A: the PKE wrapped by the HHK transform with implicit
+ * rejection; domain-separated SHAKE256 for seed formation and key
+ * derivation).  The paper does not fix the byte-level construction; this
+ * library uses, per item:
+ *   draws(m) = SHAKE256(m || 0x03) as little-endian 32-bit words: wr for r1,
+ *              wr for r2, we for e, each turned into distinct positions by
+ *              Floyd's sampling (p_i = i + floor(a_i (n - i) / 2^32), then
+ *              for i = w-1 down to 0, p_i <- i if a later p_j equals it);
+ *   Encaps:    (u, v) = Encrypt(pk, m; draws(m)),
+ *              K = SHAKE256(m || u || v || 0x04)[0, 32);
+ *   Decaps:    m' = Decrypt(y, (u, v)); ok = [Encrypt(pk, m'; draws(m'))
+ *              equals (u, v) in every word, padding bits of u included];
+ *              K = SHAKE256((ok ? m' : sigma) || u || v || 0x04)[0, 32),
+ *              the choice a select, not a branch.
+ * u and v enter the hash as their 64-bit words, little-endian.  Message m
+ * and sigma (the secret k-byte string of sk, Alg. 3) are inputs: the caller
+ * draws them.  Decapsulation has no error output for a bad ciphertext
+ * (implicit rejection); keys are HQC_KEM_KEY_BYTES bytes per item.
+ *
+ * Buffers: h, s, u, v, m, sigma, key_out 8-byte aligned, y 4-byte aligned;
+ * per item: h, s, u: u_words words; v: v_words; y: w indices; m, sigma: k
+ * bytes; key_out: 32 bytes.  workspace: device memory of at least
+ * hqc_kem_workspace_bytes(param_id, count) bytes, 8-byte aligned, owned by
+ * the caller, overwritten by the call and free again once the stream has
+ * passed it.  params->flags must be 0. */
+#define HQC_KEM_KEY_BYTES 32
+/* Workspace size for count items of one parameter set (0 for a bad id). */
+size_t hqc_kem_workspace_bytes(int param_id, size_t count);
+int hqc_kem_encaps_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                         const uint8_t *m, uint64_t *u_out, uint64_t *v_out, uint8_t *key_out,
+                         void *workspace, size_t workspace_bytes, size_t count);
+int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                         const uint32_t *y, const uint8_t *sigma, const uint64_t *u,
+                         const uint64_t *v, uint8_t *key_out, void *workspace,
+                         size_t workspace_bytes, size_t count);
+
 /* Static text for an HQC_* code. */
 const char *hqc_strerror(int code);
 /* hipError_t of the last HQC_EHIP on this thread (0 if none). */

@@ -447,7 +447,7 @@ int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks
   return run_segments(hqc::OP_KEYED, params, &s, 1, ks, key_ids);
 }
 
-static int run_encrypt(bool encrypt, const hqc_params_t *params, const hqc::EncArgs &a) {
+static int run_encrypt(int mode, const hqc_params_t *params, const hqc::EncArgs &a) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
@@ -457,13 +457,13 @@ static int run_encrypt(bool encrypt, const hqc_params_t *params, const hqc::EncA
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, hqc::encrypt_kernel_ptr(encrypt, params->param_id), 64,
+          &per_cu, hqc::encrypt_kernel_ptr(mode, params->param_id), 64,
           hqc::encrypt_lds_bytes(params->param_id));
     if (e != hipSuccess) return hip_fail(e);
     grid = cus * (per_cu < 1 ? 1 : per_cu);
   }
   if ((uint32_t)grid > a.count) grid = (int)a.count;
-  e = hqc::launch_encrypt(encrypt, params->param_id, a, grid, (hipStream_t)params->stream);
+  e = hqc::launch_encrypt(mode, params->param_id, a, grid, (hipStream_t)params->stream);
   if (e != hipSuccess) return hip_fail(e);
   return HQC_OK;
 }
@@ -489,7 +489,7 @@ int hqc_keygen_batch(const hqc_params_t *params, const uint64_t *h, const uint32
   a.y = y;
   a.s_out = s_out;
   a.count = (uint32_t)count;
-  return run_encrypt(false, params, a);
+  return run_encrypt(hqc::ENC_KEYGEN, params, a);
 }
 
 int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
@@ -526,7 +526,134 @@ int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint6
   a.u_out = u_out;
   a.v_out = v_out;
   a.count = (uint32_t)count;
-  return run_encrypt(true, params, a);
+  return run_encrypt(hqc::ENC_ARRAYS, params, a);
+}
+
+// ---- KEM -------------------------------------------------------------------------
+namespace {
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct KemLayout {
+  size_t m_off, ok_off, draws_off, total;
+};
+
+bool kem_layout(int pid, size_t count, KemLayout *o) {
+  hqc::SetInfo si;
+  if (!hqc::set_info(pid, &si)) return false;
+  o->m_off = 0;
+  o->ok_off = round256(count * (size_t)si.k);
+  o->draws_off = o->ok_off + round256(count * 4);
+  o->total = o->draws_off + count * (size_t)hqc::kem_draw_stride(pid) * 4;
+  return true;
+}
+
+// shared checks of encaps / decaps; fills si and the workspace layout
+int kem_check(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+              const uint64_t *u, const uint64_t *v, const uint8_t *key_out, void *ws,
+              size_t ws_bytes, size_t count, hqc::SetInfo *si, KemLayout *lay) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (!hqc::set_info(params->param_id, si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  if (count == 0) return HQC_OK;
+  const size_t c = count, uw = (size_t)si->u_words * 8, vw = (size_t)si->v_words * 8;
+  if (!aligned(h, 8) || !aligned(s, 8) || !aligned(u, 8) || !aligned(v, 8) ||
+      !aligned(key_out, 8) || !aligned(ws, 8))
+    return HQC_EINVAL;
+  if (!in_device_allocation(h, c * uw) || !in_device_allocation(s, c * uw) ||
+      !in_device_allocation(u, c * uw) || !in_device_allocation(v, c * vw) ||
+      !in_device_allocation(key_out, c * HQC_KEM_KEY_BYTES))
+    return HQC_EINVAL;
+  kem_layout(params->param_id, count, lay);
+  if (ws_bytes < lay->total || !in_device_allocation(ws, lay->total)) return HQC_EINVAL;
+  return HQC_OK;
+}
+
+}  // namespace
+
+size_t hqc_kem_workspace_bytes(int param_id, size_t count) {
+  KemLayout lay;
+  return kem_layout(param_id, count, &lay) ? lay.total : 0;
+}
+
+int hqc_kem_encaps_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                         const uint8_t *m, uint64_t *u_out, uint64_t *v_out, uint8_t *key_out,
+                         void *workspace, size_t workspace_bytes, size_t count) {
+  hqc::SetInfo si;
+  KemLayout lay;
+  int rc = kem_check(params, h, s, u_out, v_out, key_out, workspace, workspace_bytes, count,
+                     &si, &lay);
+  if (rc || count == 0) return rc;
+  if (!aligned(m, 8) || !in_device_allocation(m, count * (size_t)si.k)) return HQC_EINVAL;
+  const int pid = params->param_id;
+  hipStream_t st = (hipStream_t)params->stream;
+  uint32_t *draws = (uint32_t *)((char *)workspace + lay.draws_off);
+  hipError_t e = hqc::launch_kem_draws(pid, m, draws, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.h = h;
+  a.s = s;
+  a.m = m;
+  a.draws = draws;
+  a.draw_stride = hqc::kem_draw_stride(pid);
+  a.u_out = u_out;
+  a.v_out = v_out;
+  a.count = (uint32_t)count;
+  rc = run_encrypt(hqc::ENC_STREAM, params, a);
+  if (rc) return rc;
+  e = hqc::launch_kem_key(pid, m, nullptr, nullptr, u_out, v_out, key_out, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
+int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+                         const uint32_t *y, const uint8_t *sigma, const uint64_t *u,
+                         const uint64_t *v, uint8_t *key_out, void *workspace,
+                         size_t workspace_bytes, size_t count) {
+  hqc::SetInfo si;
+  KemLayout lay;
+  int rc = kem_check(params, h, s, u, v, key_out, workspace, workspace_bytes, count, &si, &lay);
+  if (rc || count == 0) return rc;
+  if (!aligned(y, 4) || !in_device_allocation(y, count * (size_t)si.w * 4)) return HQC_EINVAL;
+  if (!aligned(sigma, 8) || !in_device_allocation(sigma, count * (size_t)si.k)) return HQC_EINVAL;
+  const int pid = params->param_id;
+  hipStream_t st = (hipStream_t)params->stream;
+  uint8_t *mp = (uint8_t *)workspace + lay.m_off;
+  uint32_t *ok = (uint32_t *)((char *)workspace + lay.ok_off);
+  uint32_t *draws = (uint32_t *)((char *)workspace + lay.draws_off);
+  // m' = Decrypt(y, (u, v)) into the workspace
+  hqc_segment_t sg;
+  std::memset(&sg, 0, sizeof sg);
+  sg.param_id = pid;
+  sg.count = count;
+  sg.u = u;
+  sg.v = v;
+  sg.y = y;
+  sg.m_out = mp;
+  rc = run_segments(hqc::OP_DECRYPT, params, &sg, 1, nullptr, nullptr);
+  if (rc) return rc;
+  hipError_t e = hqc::launch_kem_draws(pid, mp, draws, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  // re-encrypt m' and compare with (u, v)
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.h = h;
+  a.s = s;
+  a.m = mp;
+  a.draws = draws;
+  a.draw_stride = hqc::kem_draw_stride(pid);
+  a.u_in = u;
+  a.v_in = v;
+  a.ok = ok;
+  a.count = (uint32_t)count;
+  rc = run_encrypt(hqc::ENC_CHECK, params, a);
+  if (rc) return rc;
+  e = hqc::launch_kem_key(pid, mp, sigma, ok, u, v, key_out, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
 }
 
 const char *hqc_strerror(int code) {

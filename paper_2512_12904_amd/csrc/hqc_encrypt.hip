@@ -1,7 +1,10 @@
 // hqc_encrypt.hip -- batched HQC key generation (Alg. 3: s = x + h*y) and
 // PKE encryption (Alg. 1: u = r1 + h*r2, v = mG + s*r2 + e truncated to
 // n1*n2 bits) for gfx950.  The randomness (h, x, y, r1, r2, e, m) is an
-// input; nothing here draws random numbers.
+// input; nothing here draws random numbers.  For the KEM, the supports r1,
+// r2, e can instead be sampled in the kernel from 32-bit draws (Floyd's
+// sampling), and the result compared with a received ciphertext instead of
+// stored (the re-encryption check of decapsulation).
 //
 // One 64-lane wavefront per item (persistent grid).  Dense operands are
 // staged as a bit-level doubled copy in LDS and multiplied by the sparse
@@ -88,14 +91,46 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
   }
 }
 
-// a*(support) + 1*(support2) -> acc (all R dwords of every lane)
+// Floyd's sampling (Bentley & Floyd 1987, positions reflected): W distinct
+// positions in [0, n) from W 32-bit draws a_i.  p_i = i + floor(a_i (n - i)
+// / 2^32); then for i = W-1 down to 0, p_i becomes i if a later p_j equals
+// it.  Position i is kept in lane i mod 64 of p[i / 64]; the loop length and
+// every access are fixed, the replacement is a select.
+template <int ID, int W>
+__device__ __forceinline__ void floyd(const uint32_t *a, uint32_t (&p)[(W + 63) / 64]) {
+  constexpr int NR = (W + 63) / 64;
+  constexpr uint32_t n = (uint32_t)Set<ID>::n;
+  const int lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const int i = 64 * c + lane;
+    const uint32_t ai = a[i < W ? i : 0];
+    p[c] = i < W ? (uint32_t)i + __umulhi(ai, n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
+  }
+#pragma unroll
+  for (int c = NR - 1; c >= 0; --c) {
+    const int top = W - 64 * c < 64 ? W - 64 * c : 64;
+#pragma unroll 1
+    for (int l = top - 1; l >= 0; --l) {
+      const int i = 64 * c + l;
+      const uint32_t pi = rdlane(p[c], l);
+      bool hit = false;
+#pragma unroll
+      for (int c2 = c; c2 < NR; ++c2) hit |= (64 * c2 + lane > i) && p[c2] == pi;
+      const bool dup = __ballot(hit) != 0ull;
+      p[c] = (dup && lane == l) ? (uint32_t)i : p[c];
+    }
+  }
+}
+
+// a*(support) + 1*(support2) -> acc (all R dwords of every lane); supports
+// held lane-strided in registers
 template <int ID, int N1, int N2>
 __device__ __forceinline__ void two_products(const uint32_t *u2, const uint32_t *one,
-                                             const uint32_t *supp1, const uint32_t *supp2,
+                                             const uint32_t (&i1)[(N1 + 63) / 64],
+                                             const uint32_t (&i2)[(N2 + 63) / 64],
                                              uint32_t (&acc)[Geo<ID>::R]) {
-  uint32_t i1[(N1 + 63) / 64], s1[(N1 + 63) / 64], i2[(N2 + 63) / 64], s2[(N2 + 63) / 64];
-  load_support<N1>(supp1, i1);
-  load_support<N2>(supp2, i2);
+  uint32_t s1[(N1 + 63) / 64], s2[(N2 + 63) / 64];
   window_shifts<ID, (N1 + 63) / 64>(i1, s1);
   window_shifts<ID, (N2 + 63) / 64>(i2, s2);
 #pragma unroll
@@ -104,23 +139,31 @@ __device__ __forceinline__ void two_products(const uint32_t *u2, const uint32_t 
   product_acc<ID, N2>(one, s2, acc);
 }
 
-// store a full n-bit polynomial (bits >= n cleared) from the lanes' dwords
-template <int ID>
-__device__ __forceinline__ void store_full(uint64_t *row, const uint32_t (&acc)[Geo<ID>::R]) {
+// store a full n-bit polynomial (bits >= n cleared) from the lanes' dwords,
+// or (CHECK) return the OR of its differences from the stored row
+template <int ID, bool CHECK>
+__device__ __forceinline__ uint32_t store_full(uint64_t *row, const uint64_t *cmp,
+                                               const uint32_t (&acc)[Geo<ID>::R]) {
   using G = Geo<ID>;
   uint32_t *dst = (uint32_t *)row;
+  const uint32_t *src = (const uint32_t *)cmp;
   const int lane = lane_id();
+  uint32_t diff = 0;
 #pragma unroll
   for (int j = 0; j < G::R; ++j) {
     const int d = lane * G::R + j;
     if (d < 2 * G::U_WORDS) {
       uint32_t val = d < G::DW ? acc[j] : (d == G::DW ? acc[j] & ((1u << G::NB) - 1u) : 0u);
-      dst[d] = val;
+      if constexpr (CHECK)
+        diff |= src[d] ^ val;
+      else
+        dst[d] = val;
     }
   }
+  return diff;
 }
 
-template <int ID, bool ENCRYPT>
+template <int ID, int MODE>
 __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32_t *lds,
                                          uint32_t exp4, uint32_t log4, uint32_t pat) {
   using G = Geo<ID>;
@@ -131,19 +174,35 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   uint32_t acc[G::R];
   const size_t nw = (size_t)G::U_WORDS;
 
-  if constexpr (!ENCRYPT) {
+  if constexpr (MODE == ENC_KEYGEN) {
     // Alg. 3: s = x + h*y
+    constexpr int NR = (G::w + 63) / 64;
+    uint32_t iy[NR], ix[NR];
+    load_support<G::w>(a.y + (size_t)item * G::w, iy);
+    load_support<G::w>(a.x + (size_t)item * G::w, ix);
     stage_dense<ID>(a.h + item * nw, u2);
-    two_products<ID, G::w, G::w>(u2, one, a.y + (size_t)item * G::w, a.x + (size_t)item * G::w, acc);
-    store_full<ID>(a.s_out + item * nw, acc);
+    two_products<ID, G::w, G::w>(u2, one, iy, ix, acc);
+    store_full<ID, false>(a.s_out + item * nw, nullptr, acc);
     wave_sync();
     return;
   } else {
-    constexpr int WR = Set<ID>::wr;
+    constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
+    constexpr bool CHECK = MODE == ENC_CHECK;
+    uint32_t ir1[(WR + 63) / 64], ir2[(WR + 63) / 64], ie[(WE + 63) / 64];
+    if constexpr (MODE == ENC_ARRAYS) {
+      load_support<WR>(a.r1 + (size_t)item * WR, ir1);
+      load_support<WR>(a.r2 + (size_t)item * WR, ir2);
+      load_support<WE>(a.e + (size_t)item * WE, ie);
+    } else {
+      const uint32_t *dr = a.draws + (size_t)item * a.draw_stride;
+      floyd<ID, WR>(dr, ir1);
+      floyd<ID, WR>(dr + WR, ir2);
+      floyd<ID, WE>(dr + 2 * WR, ie);
+    }
     // Alg. 1: u = r1 + h*r2
     stage_dense<ID>(a.h + item * nw, u2);
-    two_products<ID, WR, WR>(u2, one, a.r2 + (size_t)item * WR, a.r1 + (size_t)item * WR, acc);
-    store_full<ID>(a.u_out + item * nw, acc);
+    two_products<ID, WR, WR>(u2, one, ir2, ir1, acc);
+    uint32_t diff = store_full<ID, CHECK>(a.u_out + item * nw, a.u_in + item * nw, acc);
 
     // Reed-Solomon parity of m: x^{2d} m(x) mod g(x), register j in lane j
     constexpr int TD = G::TD;
@@ -168,9 +227,9 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     // v = mG + s*r2 + e, first n1*n2 bits
     wave_sync();
     stage_dense<ID>(a.s + item * nw, u2);
-    two_products<ID, WR, Set<ID>::we>(u2, one, a.r2 + (size_t)item * WR,
-                                      a.e + (size_t)item * Set<ID>::we, acc);
+    two_products<ID, WR, WE>(u2, one, ir2, ie, acc);
     uint32_t *dst = (uint32_t *)(a.v_out + item * (size_t)G::V_WORDS);
+    const uint32_t *vin = (const uint32_t *)(a.v_in + item * (size_t)G::V_WORDS);
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
       const int d = lane * G::R + j;
@@ -180,13 +239,22 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       const uint32_t p = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((c & 31u) << 2), (int)pat);
       const uint32_t flip = ((c >> 7) ^ ((c >> 5) & (uint32_t)w) ^ ((c >> 6) & ((uint32_t)w >> 1))) & 1u;
       const uint32_t word = p ^ (0u - flip);
-      if (d < G::W32) dst[d] = acc[j] ^ word;
+      if (d < G::W32) {
+        if constexpr (CHECK)
+          diff |= vin[d] ^ acc[j] ^ word;
+        else
+          dst[d] = acc[j] ^ word;
+      }
+    }
+    if constexpr (CHECK) {
+      const bool same = __ballot(diff != 0u) == 0ull;
+      if (lane == 0) a.ok[item] = same ? 1u : 0u;
     }
     wave_sync();
   }
 }
 
-template <bool ENCRYPT, int ID>
+template <int MODE, int ID>
 __global__ __launch_bounds__(64) void hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
@@ -204,7 +272,7 @@ __global__ __launch_bounds__(64) void hqc_encrypt_kernel(EncArgs a) {
   }
   wave_sync();
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
-    run_item<ID, ENCRYPT>(a, item, lds, exp4, log4, pat);
+    run_item<ID, MODE>(a, item, lds, exp4, log4, pat);
 }
 
 template <int ID> size_t enc_lds() {
@@ -214,18 +282,20 @@ template <int ID> size_t enc_lds() {
 
 }  // namespace
 
-const void *encrypt_kernel_ptr(bool encrypt, int pid) {
-  if (encrypt) {
-    switch (pid) {
-      case 1: return (const void *)&hqc_encrypt_kernel<true, 1>;
-      case 3: return (const void *)&hqc_encrypt_kernel<true, 3>;
-      default: return (const void *)&hqc_encrypt_kernel<true, 5>;
-    }
-  }
+template <int MODE> const void *enc_ptr(int pid) {
   switch (pid) {
-    case 1: return (const void *)&hqc_encrypt_kernel<false, 1>;
-    case 3: return (const void *)&hqc_encrypt_kernel<false, 3>;
-    default: return (const void *)&hqc_encrypt_kernel<false, 5>;
+    case 1: return (const void *)&hqc_encrypt_kernel<MODE, 1>;
+    case 3: return (const void *)&hqc_encrypt_kernel<MODE, 3>;
+    default: return (const void *)&hqc_encrypt_kernel<MODE, 5>;
+  }
+}
+
+const void *encrypt_kernel_ptr(int mode, int pid) {
+  switch (mode) {
+    case ENC_KEYGEN: return enc_ptr<ENC_KEYGEN>(pid);
+    case ENC_ARRAYS: return enc_ptr<ENC_ARRAYS>(pid);
+    case ENC_STREAM: return enc_ptr<ENC_STREAM>(pid);
+    default: return enc_ptr<ENC_CHECK>(pid);
   }
 }
 
@@ -237,10 +307,10 @@ size_t encrypt_lds_bytes(int pid) {
   }
 }
 
-hipError_t launch_encrypt(bool encrypt, int pid, const EncArgs &a, int grid, hipStream_t stream) {
+hipError_t launch_encrypt(int mode, int pid, const EncArgs &a, int grid, hipStream_t stream) {
   EncArgs copy = a;
   void *args[] = {&copy};
-  return hipLaunchKernel(encrypt_kernel_ptr(encrypt, pid), dim3((unsigned)grid), dim3(64), args,
+  return hipLaunchKernel(encrypt_kernel_ptr(mode, pid), dim3((unsigned)grid), dim3(64), args,
                          encrypt_lds_bytes(pid), stream);
 }
 

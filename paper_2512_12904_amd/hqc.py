@@ -29,7 +29,8 @@ EXPORTS = (
     "hqc_decode_mixed", "hqc_keystore_create", "hqc_keystore_put", "hqc_keystore_put_many",
     "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
-    "hqc_encrypt_batch",
+    "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
+    "hqc_kem_decaps_batch",
 )
 
 
@@ -88,6 +89,12 @@ def lib():
         L.hqc_default_grid.argtypes = [ctypes.c_int]
         L.hqc_keygen_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, sz]
         L.hqc_encrypt_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp, sz]
+        L.hqc_kem_workspace_bytes.restype = ctypes.c_size_t
+        L.hqc_kem_workspace_bytes.argtypes = [ctypes.c_int, sz]
+        L.hqc_kem_encaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, sz,
+                                           sz]
+        L.hqc_kem_decaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp,
+                                           sz, sz]
         L.hqc_shutdown.restype = None
         L.hqc_shutdown.argtypes = []
         _lib = L
@@ -304,3 +311,70 @@ def default_grid(pid):
 
 def shutdown():
     lib().hqc_shutdown()
+
+
+KEM_KEY_BYTES = 32
+
+
+def kem_workspace_bytes(pid, count):
+    return lib().hqc_kem_workspace_bytes(pid, count)
+
+
+def _workspace(pid, count, device, workspace):
+    need = kem_workspace_bytes(pid, count)
+    if workspace is None:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=device)
+    if workspace.numel() < need:
+        raise ValueError("workspace holds %d bytes, %d needed" % (workspace.numel(), need))
+    return workspace
+
+
+def kem_encaps_batch(pid, h, s, m, u_out=None, v_out=None, key_out=None, workspace=None,
+                     grid=0, stream=None):
+    """KEM encapsulation of the caller's messages m[i] under (h[i], s[i]):
+    returns (u, v, key); the construction is documented in hqc_gpu.h."""
+    sz = sizes(pid)
+    count = h.shape[0]
+    dev = h.device
+    if u_out is None:
+        u_out = torch.empty((count, sz["u_words"]), dtype=torch.int64, device=dev)
+    if v_out is None:
+        v_out = torch.empty((count, sz["v_words"]), dtype=torch.int64, device=dev)
+    if key_out is None:
+        key_out = torch.empty((count, KEM_KEY_BYTES), dtype=torch.uint8, device=dev)
+    ws = _workspace(pid, count, dev, workspace)
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_kem_encaps_batch(
+        ctypes.byref(p), _dev(h, torch.int64, "h", (count, sz["u_words"])),
+        _dev(s, torch.int64, "s", (count, sz["u_words"])),
+        _dev(m, torch.uint8, "m", (count, sz["k"])),
+        _dev(u_out, torch.int64, "u_out", (count, sz["u_words"])),
+        _dev(v_out, torch.int64, "v_out", (count, sz["v_words"])),
+        _dev(key_out, torch.uint8, "key_out", (count, KEM_KEY_BYTES)),
+        _dev(ws, torch.uint8, "workspace"), ws.numel(), count)
+    _check(rc, "hqc_kem_encaps_batch")
+    return u_out, v_out, key_out
+
+
+def kem_decaps_batch(pid, h, s, y, sigma, u, v, key_out=None, workspace=None, grid=0,
+                     stream=None, tile=0):
+    """KEM decapsulation: key[i] from (u[i], v[i]) with the secret (y[i],
+    sigma[i]) and public (h[i], s[i]); implicit rejection (no error output)."""
+    sz = sizes(pid)
+    count = u.shape[0]
+    dev = u.device
+    if key_out is None:
+        key_out = torch.empty((count, KEM_KEY_BYTES), dtype=torch.uint8, device=dev)
+    ws = _workspace(pid, count, dev, workspace)
+    p = _params(pid, 0, grid, stream, tile)
+    rc = lib().hqc_kem_decaps_batch(
+        ctypes.byref(p), _dev(h, torch.int64, "h", (count, sz["u_words"])),
+        _dev(s, torch.int64, "s", (count, sz["u_words"])),
+        _dev(y, torch.int32, "y", (count, sz["w"])),
+        _dev(sigma, torch.uint8, "sigma", (count, sz["k"])),
+        _dev(u, torch.int64, "u", (count, sz["u_words"])),
+        _dev(v, torch.int64, "v", (count, sz["v_words"])),
+        _dev(key_out, torch.uint8, "key_out", (count, KEM_KEY_BYTES)),
+        _dev(ws, torch.uint8, "workspace"), ws.numel(), count)
+    _check(rc, "hqc_kem_decaps_batch")
+    return key_out

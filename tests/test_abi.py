@@ -97,3 +97,14 @@ def test_host_pointer_rejected_without_gpu(gpu_lib):
     buf = np.zeros(4096, np.uint64)
     ptr = ctypes.c_void_p(buf.ctypes.data)
     assert L.hqc_decode_batch(ctypes.byref(p), ptr, ptr, 1) == gpu_lib.HQC_EINVAL
+
+
+def test_kem_workspace_size(gpu_lib):
+    L = gpu_lib.lib()
+    assert L.hqc_kem_workspace_bytes(2, 10) == 0
+    for pid in (1, 3, 5):
+        a, b = L.hqc_kem_workspace_bytes(pid, 1), L.hqc_kem_workspace_bytes(pid, 1000)
+        assert 0 < a < b
+        # m', flags and the draw rows (2 wr + we words, whole squeeze blocks) of every item
+        sz = gpu_lib.sizes(pid)
+        assert b >= 1000 * (sz["k"] + 4 + 4 * (2 * sz["wr"] + sz["we"]))
