@@ -82,6 +82,44 @@ def make_inputs(pid, count, seed, device):
     return u, v, yd, md, times
 
 
+def kem_bench(hqc, pid, count, seed, device, reps=3):
+    """KEM encapsulation and decapsulation of count items (own key per item),
+    timed with HIP events on the launch stream (reps launches each after one
+    warm-up); every decapsulated key must equal the encapsulated one."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    s = dict(SETS[pid])
+    h, x, y = synth.keys(seed, pid, s, count)
+    m = synth.encryptions(seed, pid, s, count)[0]
+    sigma = synth.words(seed ^ 0x5157, (count, s["k"] // 8)).view(np.uint8)
+    t = lambda a, dt: torch.from_numpy(a.view(dt) if a.dtype != np.uint8 else a).to(device)
+    hd, yd, md, sg = t(h, np.int64), t(y, np.int32), t(m, np.uint8), t(sigma, np.uint8)
+    sd = hqc.keygen_batch(pid, hd, t(x, np.int32), yd)
+    ws = torch.empty(hqc.kem_workspace_bytes(pid, count), dtype=torch.uint8, device=device)
+    u, v, key = hqc.kem_encaps_batch(pid, hd, sd, md, workspace=ws)
+    key2 = hqc.kem_decaps_batch(pid, hd, sd, yd, sg, u, v, workspace=ws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        hqc.kem_encaps_batch(pid, hd, sd, md, u_out=u, v_out=v, key_out=key, workspace=ws)
+        ev[1 + i].record()
+    for i in range(reps):
+        hqc.kem_decaps_batch(pid, hd, sd, yd, sg, u, v, key_out=key2, workspace=ws)
+        ev[1 + reps + i].record()
+    torch.cuda.synchronize()
+    enc = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    dec = [ev[reps + i].elapsed_time(ev[reps + i + 1]) for i in range(reps)]
+    r = {"kem_encaps_ms": sum(enc) / reps, "kem_decaps_ms": sum(dec) / reps,
+         "kem_encaps_per_s": count / (sum(enc) / reps / 1e3),
+         "kem_decaps_per_s": count / (sum(dec) / reps / 1e3),
+         "kem_all_keys_match": bool(torch.equal(key, key2))}
+    del hd, yd, md, sg, sd, ws, u, v, key, key2
+    torch.cuda.empty_cache()
+    return r
+
+
 def time_batched(hqc, pid, u, v, y, out, steps, warmup):
     """Per-launch device times (ms) from HIP events on the launch stream."""
     import torch
@@ -226,7 +264,8 @@ def serving_bench(device, loads, seconds, streams=4, budget=1 << 30):
 
 
 def main_checks(results):
-    return all(r.get("all_messages_recovered", False) for r in results.values())
+    return all(r.get("all_messages_recovered", False) and r.get("kem_all_keys_match", True)
+               for r in results.values())
 
 
 def main():
@@ -241,6 +280,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop run")
+    ap.add_argument("--no-kem", action="store_true",
+                    help="skip the KEM encapsulation / decapsulation timing")
     ap.add_argument("--serving-seconds", type=float, default=2.0)
     ap.add_argument("--tile", type=int, default=0, help="items per workgroup (0 = library)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups (0 = library)")
@@ -283,6 +324,11 @@ def main():
             r["batched_over_per_item"] = r["decrypts_per_s"] / r["per_item_decrypts_per_s"]
         ops = op_model(pid) * args.count
         r["alu_frac"] = ops / (r["ms_mean"] / 1e3) / PEAK_INT_OPS
+        if not args.no_kem:
+            del u, v, y, m, out
+            torch.cuda.empty_cache()
+            u = v = y = m = out = None
+            r.update(kem_bench(hqc, pid, args.count, 0xC0DE + pid, dev))
         r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
         results[pid] = r
         del u, v, y, m, out
@@ -290,7 +336,7 @@ def main():
 
     main_r = results[sets[0]]
     if not main_checks(results):
-        print("decrypted messages differ from the encrypted ones", file=sys.stderr)
+        print("decrypted messages or KEM keys differ from the encrypted ones", file=sys.stderr)
     pid0 = sets[0]
     ops_launch = op_model(pid0) * args.count
     achieved = ops_launch / (main_r["ms_mean"] / 1e3)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hqc_internal.h"
+#include "hqc_internal_enc.h"
 
 namespace {
 

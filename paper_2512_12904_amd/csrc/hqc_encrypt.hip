@@ -17,6 +17,7 @@
 // symbol: a 32-entry pattern table for the low five message bits (read with
 // ds_bpermute_b32) and a whole-dword complement for bits 5-7.
 #include "hqc_device.h"
+#include "hqc_internal_enc.h"
 
 namespace hqc {
 namespace {
@@ -207,12 +208,13 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     // Reed-Solomon parity of m: x^{2d} m(x) mod g(x), register j in lane j
     constexpr int TD = G::TD;
     const uint8_t *mrow = a.m + (size_t)item * G::k;
+    const uint32_t mlane = lane < G::k ? (uint32_t)mrow[lane] : 0u;  // byte t of m in lane t
     const uint32_t lg = kRsGen.lg[gen_slot<ID>()][lane];
     const uint32_t gnz = kRsGen.nz[gen_slot<ID>()][lane];
     uint32_t reg = 0;
 #pragma unroll 1
     for (int t = G::k - 1; t >= 0; --t) {
-      const uint32_t mt = __builtin_amdgcn_readfirstlane((uint32_t)mrow[t]);
+      const uint32_t mt = rdlane(mlane, t);
       const uint32_t fb = (mt ^ rdlane(reg, TD - 1)) & 0xFFu;
       const uint32_t lfb = tab(log4, fb);
       uint32_t prod = tab(exp4, red255(lfb + lg));
@@ -222,7 +224,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       reg = lane < TD ? ((lane > 0 ? prev : 0u) ^ prod) : 0u;
     }
     if (lane < TD) sym[lane] = (uint8_t)reg;
-    if (lane < G::k) sym[TD + lane] = mrow[lane];
+    if (lane < G::k) sym[TD + lane] = (uint8_t)mlane;
 
     // v = mG + s*r2 + e, first n1*n2 bits
     wave_sync();

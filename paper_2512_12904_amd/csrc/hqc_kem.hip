@@ -17,6 +17,7 @@
 #include <utility>
 
 #include "hqc_device.h"
+#include "hqc_internal_enc.h"
 
 namespace hqc {
 namespace {
