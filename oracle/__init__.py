@@ -12,8 +12,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hqc_oracle.c")
-_SOURCES = [_SRC, os.path.join(_HERE, "kem_oracle.c")]
-_HEADERS = [os.path.join(_HERE, "hqc_oracle.h"), os.path.join(_HERE, "kem_oracle.h")]
+_SOURCES = [_SRC, os.path.join(_HERE, "kem_oracle.c"), os.path.join(_HERE, "ring_oracle.c")]
+_HEADERS = [os.path.join(_HERE, "hqc_oracle.h"), os.path.join(_HERE, "kem_oracle.h"),
+            os.path.join(_HERE, "ring_oracle.h")]
 _SO = os.path.join(_HERE, "libhqc_oracle.so")
 _lib = None
 
@@ -82,6 +83,12 @@ def lib():
         L.hqco_decrypt_batch.argtypes = [ctypes.c_int, ctypes.c_size_t, U32P, I64P, U64P, U64P,
                                          U8P, ctypes.c_int]
         L.hqco_keccak_f1600.argtypes = [U64P]
+        L.hqco_ring_levels.restype = ctypes.c_int
+        L.hqco_ring_levels.argtypes = [ctypes.c_int]
+        L.hqco_ring_mul_dense.argtypes = [ctypes.c_int, U64P, U64P, U64P]
+        L.hqco_ring_mul_sparse.argtypes = [ctypes.c_int, U64P, U64P, U64P]
+        L.hqco_ring_mul.restype = ctypes.c_int
+        L.hqco_ring_mul.argtypes = [ctypes.c_int, U64P, U64P, U64P, ctypes.c_uint32]
         L.hqco_shake256.argtypes = [U8P, ctypes.c_size_t, U8P, ctypes.c_size_t]
         L.hqco_fixed_weight.argtypes = [ctypes.c_int, ctypes.c_int, U32P, U32P]
         L.hqco_kem_seed_words.argtypes = [ctypes.c_int, U8P, U32P]
@@ -422,3 +429,35 @@ def kem_decaps_batch(pid, h, s, y, sigma, u, v, nthreads=None):
                                        _p(sigma, U8P), _p(u, U64P), _p(v, U64P), _p(key, U8P),
                                        _p(ok, I32P), nthreads or default_threads()))
     return key, ok.astype(bool)
+
+
+# ---- adaptive ring multiplication (ring_oracle.c) ------------------------------
+
+def ring_levels(uwords):
+    return lib().hqco_ring_levels(uwords)
+
+
+def _ring_args(n, a, b):
+    U = (n + 63) // 64
+    a, b = _u64(a), _u64(b)
+    assert a.shape == (U,) and b.shape == (U,)
+    return a, b, np.zeros(U, np.uint64)
+
+
+def ring_mul_dense(n, a, b):
+    a, b, out = _ring_args(n, a, b)
+    lib().hqco_ring_mul_dense(n, _p(a, U64P), _p(b, U64P), _p(out, U64P))
+    return out
+
+
+def ring_mul_sparse(n, a, b):
+    a, b, out = _ring_args(n, a, b)
+    lib().hqco_ring_mul_sparse(n, _p(a, U64P), _p(b, U64P), _p(out, U64P))
+    return out
+
+
+def ring_mul(n, a, b, threshold):
+    """(out, path): path 0 = sparse (weight(a) <= threshold), 1 = dense."""
+    a, b, out = _ring_args(n, a, b)
+    path = lib().hqco_ring_mul(n, _p(a, U64P), _p(b, U64P), _p(out, U64P), threshold)
+    return out, path
