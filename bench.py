@@ -120,6 +120,44 @@ def kem_bench(hqc, pid, count, seed, device, reps=3):
     return r
 
 
+def ring_sweep(hqc, pid, count, device, weights=(75, 256, 512, 1024, 2048, 3072, 4096), reps=3):
+    """Adaptive ring multiplication (Sec. III-B): per-item device time of the
+    sparse path (forced, threshold = max) and of the dense path (forced,
+    threshold = 0) on count items whose first operand has each weight, and
+    the smallest swept weight at which the dense path is faster."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    s = dict(SETS[pid])
+    n, U = s["n"], (s["n"] + 63) // 64
+    b = torch.from_numpy(synth.words(0xB0B + pid, (count, U)).view(np.int64)).to(device)
+    ws = torch.empty(hqc.ring_workspace_bytes(pid, count), dtype=torch.uint8, device=device)
+    out = torch.empty((count, U), dtype=torch.int64, device=device)
+    path = torch.empty(count, dtype=torch.uint8, device=device)
+    rows = []
+    for w in weights:
+        a = np.zeros((count, 64 * U), np.uint8)
+        for i in range(count):
+            a[i, synth.fixed_weight(0xA0A0 + 7919 * w + i, n, w)] = 1
+        ad = torch.from_numpy(np.packbits(a, axis=1, bitorder="little").view(np.int64)).to(device)
+        res = {"weight": w}
+        for name, thr in (("sparse", 0xFFFFFFFF), ("dense", 0)):
+            hqc.ring_mul_batch(pid, ad, b, out=out, threshold=thr, path_out=path, workspace=ws)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            ev[0].record()
+            for i in range(reps):
+                hqc.ring_mul_batch(pid, ad, b, out=out, threshold=thr, path_out=path, workspace=ws)
+                ev[i + 1].record()
+            torch.cuda.synchronize()
+            ms = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(reps)) / reps
+            res[name + "_us_per_item"] = ms * 1e3 / count
+        rows.append(res)
+        del ad
+    cross = next((r["weight"] for r in rows if r["dense_us_per_item"] < r["sparse_us_per_item"]), None)
+    return {"items": count, "sweep": rows, "crossover_weight": cross,
+            "default_threshold": hqc.ring_default_threshold(pid)}
+
+
 def time_batched(hqc, pid, u, v, y, out, steps, warmup):
     """Per-launch device times (ms) from HIP events on the launch stream."""
     import torch
@@ -280,6 +318,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop run")
+    ap.add_argument("--ring-sweep", type=int, default=0, metavar="ITEMS",
+                    help="only time the adaptive ring multiplication's two paths over "
+                         "first-operand weights (ITEMS items per set) and print them")
     ap.add_argument("--no-kem", action="store_true",
                     help="skip the KEM encapsulation / decapsulation timing")
     ap.add_argument("--serving-seconds", type=float, default=2.0)
@@ -303,6 +344,10 @@ def main():
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy, dev)
     sets = [int(x) for x in args.sets.split(",")]
+    if args.ring_sweep:
+        print(json.dumps({"ring_sweep": {"HQC-%d" % pid: ring_sweep(hqc, pid, args.ring_sweep, dev)
+                                         for pid in sets}}), flush=True)
+        return
     results = {}
     for pid in sets:
         u, v, y, m, gen = make_inputs(pid, args.count, 0xBE00 + pid, dev)

@@ -206,6 +206,32 @@ int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const ui
                          const uint64_t *v, uint8_t *key_out, void *workspace,
                          size_t workspace_bytes, size_t count);
 
+/* ---- Adaptive ring multiplication (Sec. III-B, threshold-aware
+ * scheduling): out[i] = a[i] * b[i] in GF(2)[X]/(X^n - 1) for dense n-bit
+ * rows (u_words words each; bits >= n of a and b ignored, of out zero).
+ * Item i takes the sparse path of Eq. (1) (XOR of rotations of b[i] by the
+ * support of a[i]) when weight(a[i]) <= threshold and <= HQC_RING_SPARSE_MAX,
+ * else the dense path (Karatsuba over 64-bit words, then reduction mod
+ * X^n - 1).  Both give the same product.  path_out (nullable, count bytes):
+ * 0 sparse, 1 dense.  The path depends on the weight of a and the sparse
+ * path's timing on its support: for operands whose weight and support are
+ * public (the PKE and KEM entry points take supports directly and run in
+ * constant time).
+ *
+ * a, b, out 8-byte aligned.  workspace: device memory, 8-byte aligned, of at
+ * least hqc_ring_workspace_bytes(param_id, count, 1) bytes; with
+ * hqc_ring_workspace_bytes(param_id, count, count) bytes every dense item
+ * is processed in one pass, with less in chunks.  params->flags must be 0;
+ * params->grid sets the sparse kernel's persistent grid (0 = occupancy). */
+#define HQC_RING_SPARSE_MAX 4096
+size_t hqc_ring_workspace_bytes(int param_id, size_t count, size_t chunk_items);
+/* The weight threshold calibrated for the parameter set (the measured
+ * cross-over of the two paths on MI355X); 0 for a bad id. */
+uint32_t hqc_ring_default_threshold(int param_id);
+int hqc_ring_mul_batch(const hqc_params_t *params, const uint64_t *a, const uint64_t *b,
+                       uint64_t *out, uint8_t *path_out, uint32_t threshold, void *workspace,
+                       size_t workspace_bytes, size_t count);
+
 /* Static text for an HQC_* code. */
 const char *hqc_strerror(int code);
 /* hipError_t of the last HQC_EHIP on this thread (0 if none). */

@@ -657,6 +657,66 @@ int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const ui
   return HQC_OK;
 }
 
+// ---- adaptive ring multiplication ----------------------------------------------------
+size_t hqc_ring_workspace_bytes(int param_id, size_t count, size_t chunk_items) {
+  if (count == 0 || chunk_items == 0) return 0;
+  return hqc::ring_workspace_bytes(param_id, count, chunk_items);
+}
+
+// Measured on MI355X (bench.py --ring-sweep 2048): the sparse path stays
+// faster than the dense one up to the sparse list's capacity for every set
+// (HQC-1 0.42 vs 0.46 us per item at weight 4096), so the threshold is that
+// capacity.
+uint32_t hqc_ring_default_threshold(int param_id) {
+  switch (param_id) {
+    case 1:
+    case 3:
+    case 5: return HQC_RING_SPARSE_MAX;
+    default: return 0;
+  }
+}
+
+int hqc_ring_mul_batch(const hqc_params_t *params, const uint64_t *a, const uint64_t *b,
+                       uint64_t *out, uint8_t *path_out, uint32_t threshold, void *workspace,
+                       size_t workspace_bytes, size_t count) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  if (count == 0) return HQC_OK;
+  const size_t c = count, uw = (size_t)si.u_words * 8;
+  if (!aligned(a, 8) || !aligned(b, 8) || !aligned(out, 8) || !aligned(workspace, 8))
+    return HQC_EINVAL;
+  if (!in_device_allocation(a, c * uw) || !in_device_allocation(b, c * uw) ||
+      !in_device_allocation(out, c * uw))
+    return HQC_EINVAL;
+  if (path_out && !in_device_allocation(path_out, c)) return HQC_EINVAL;
+  const size_t need = hqc::ring_workspace_bytes(params->param_id, count, 1);
+  if (workspace_bytes < need || !in_device_allocation(workspace, workspace_bytes))
+    return HQC_EINVAL;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  int grid = params->grid;
+  if (grid <= 0) {
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, hqc::ring_sparse_kernel_ptr(params->param_id), 64,
+          hqc::ring_sparse_lds(params->param_id));
+    if (e != hipSuccess) return hip_fail(e);
+    grid = cus * (per_cu < 1 ? 1 : per_cu);
+  }
+  if ((size_t)grid > count) grid = (int)count;
+  e = hqc::launch_ring_mul(params->param_id, a, b, out, path_out, threshold, workspace,
+                           workspace_bytes, (uint32_t)count, grid, (hipStream_t)params->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return HQC_OK;
+}
+
 const char *hqc_strerror(int code) {
   switch (code) {
     case HQC_OK: return "success";

@@ -43,4 +43,13 @@ hipError_t launch_kem_draws(int pid, const uint8_t *m, uint32_t *draws, uint32_t
 hipError_t launch_kem_key(int pid, const uint8_t *m, const uint8_t *sigma, const uint32_t *ok,
                           const uint64_t *u, const uint64_t *v, uint8_t *key, uint32_t count,
                           hipStream_t stream);
+// Adaptive ring multiplication (hqc_ring.hip).  Workspace: a header for
+// count items, then the dense scratch of chunk_items items.
+size_t ring_workspace_bytes(int pid, size_t count, size_t chunk_items);
+size_t ring_sparse_lds(int pid);
+const void *ring_sparse_kernel_ptr(int pid);
+hipError_t launch_ring_mul(int pid, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                           uint8_t *path_out, uint32_t threshold, void *ws, size_t ws_bytes,
+                           uint32_t count, int grid, hipStream_t stream);
+
 }  // namespace hqc

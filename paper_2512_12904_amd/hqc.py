@@ -30,7 +30,8 @@ EXPORTS = (
     "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
     "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
-    "hqc_kem_decaps_batch",
+    "hqc_kem_decaps_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
+    "hqc_ring_mul_batch",
 )
 
 
@@ -95,6 +96,12 @@ def lib():
                                            sz]
         L.hqc_kem_decaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp,
                                            sz, sz]
+        L.hqc_ring_workspace_bytes.restype = ctypes.c_size_t
+        L.hqc_ring_workspace_bytes.argtypes = [ctypes.c_int, sz, sz]
+        L.hqc_ring_default_threshold.restype = ctypes.c_uint32
+        L.hqc_ring_default_threshold.argtypes = [ctypes.c_int]
+        L.hqc_ring_mul_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, ctypes.c_uint32,
+                                         vp, sz, sz]
         L.hqc_shutdown.restype = None
         L.hqc_shutdown.argtypes = []
         _lib = L
@@ -378,3 +385,42 @@ def kem_decaps_batch(pid, h, s, y, sigma, u, v, key_out=None, workspace=None, gr
         _dev(ws, torch.uint8, "workspace"), ws.numel(), count)
     _check(rc, "hqc_kem_decaps_batch")
     return key_out
+
+
+RING_SPARSE_MAX = 4096
+
+
+def ring_workspace_bytes(pid, count, chunk_items=None):
+    return lib().hqc_ring_workspace_bytes(pid, count, count if chunk_items is None else chunk_items)
+
+
+def ring_default_threshold(pid):
+    return lib().hqc_ring_default_threshold(pid)
+
+
+def ring_mul_batch(pid, a, b, out=None, threshold=None, path_out=None, workspace=None,
+                   chunk_items=None, grid=0, stream=None):
+    """out[i] = a[i] * b[i] in GF(2)[X]/(X^n - 1) (Sec. III-B adaptive path:
+    sparse Eq. (1) when weight(a[i]) <= threshold, else dense Karatsuba).
+    Returns (out, path) with path[i] = 0 sparse / 1 dense."""
+    sz = sizes(pid)
+    count = a.shape[0]
+    dev = a.device
+    if out is None:
+        out = torch.empty((count, sz["u_words"]), dtype=torch.int64, device=dev)
+    if path_out is None:
+        path_out = torch.empty(count, dtype=torch.uint8, device=dev)
+    if threshold is None:
+        threshold = ring_default_threshold(pid)
+    if workspace is None:
+        workspace = torch.empty(max(8, ring_workspace_bytes(pid, count, chunk_items)),
+                                dtype=torch.uint8, device=dev)
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_ring_mul_batch(
+        ctypes.byref(p), _dev(a, torch.int64, "a", (count, sz["u_words"])),
+        _dev(b, torch.int64, "b", (count, sz["u_words"])),
+        _dev(out, torch.int64, "out", (count, sz["u_words"])),
+        _dev(path_out, torch.uint8, "path_out", (count,)), threshold,
+        _dev(workspace, torch.uint8, "workspace"), workspace.numel(), count)
+    _check(rc, "hqc_ring_mul_batch")
+    return out, path_out
