@@ -53,8 +53,11 @@ template <int ID> struct Geo {
   static constexpr bool COMPACT = ID == 5;
   static constexpr int TROWS = COMPACT ? 32 : 64;    // items per (sub-)tile
   static constexpr int RB_OFF = COMPACT ? 0 : U2;    // dword offset of the received word
+  // HQC-1 keeps the received words of RMG = 4 items and RM-decodes their
+  // 4 x 46 = 184 blocks in 3 passes of 64 lanes instead of 4 passes of 46
+  static constexpr int RMG = ID == 1 ? 4 : 1;
   static constexpr int A_BYTES =
-      (cmax(4 * (COMPACT ? cmax(U2, RB) : U2 + RB), TROWS * RS_BYTES_LANE) + 15) / 16 * 16;
+      (cmax(4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB), TROWS * RS_BYTES_LANE) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
   static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
   static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");

@@ -175,12 +175,11 @@ __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRe
 
 template <int ID, int OP>
 __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *lds,
-                                              const uint32_t *vsrc) {
+                                              uint32_t *rb, const uint32_t *vsrc) {
   using G = Geo<ID>;
   using IR = ItemRegs<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
-  uint32_t *rb = lds + G::RB_OFF;
 
   if (!G::COMPACT || OP == OP_DECODE) {
 #pragma unroll
@@ -525,21 +524,43 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   // leaving the latency to the other wavefronts on the SIMD
   ItemRegs<ID> regs;
   if constexpr (!G::COMPACT) prefetch<ID, OP>(sg, item0, regs);
+  int passes = 0;  // RM passes done for the current group
   for (int it = 0; it < nt; ++it) {
     const uint32_t cur = item0 + (uint32_t)it;
+    const int gi = it % G::RMG;  // slot of this item's received word
     if constexpr (G::COMPACT) prefetch<ID, OP>(sg, cur, regs);
-    received_word<ID, OP>(regs, lds, (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS));
+    received_word<ID, OP>(regs, lds, lds + G::RB_OFF + gi * G::RB,
+                          (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS));
     wave_sync();
     if (!G::COMPACT && it + 1 < nt) prefetch<ID, OP>(sg, cur + 1, regs);
-    const uint32_t *rb = lds + G::RB_OFF;
+    if constexpr (G::RMG == 1) {
+      const uint32_t *rb = lds + G::RB_OFF;
 #pragma unroll
-    for (int pass = 0; pass < G::SYMREG; ++pass) {
-      const int j = lane + 64 * pass;
-      const int jj = j < G::n1 ? j : G::n1 - 1;
-      const uint32_t sbyte = rm_decode_block<G::MULT>(rb + jj * G::BSTR);
-      if (j < G::n1) sym[it * G::SSTR + j] = (uint8_t)sbyte;
+      for (int pass = 0; pass < G::SYMREG; ++pass) {
+        const int j = lane + 64 * pass;
+        const int jj = j < G::n1 ? j : G::n1 - 1;
+        const uint32_t sbyte = rm_decode_block<G::MULT>(rb + jj * G::BSTR);
+        if (j < G::n1) sym[it * G::SSTR + j] = (uint8_t)sbyte;
+      }
+      wave_sync();
+    } else {
+      // the group's blocks, flat index q n1 + b for block b of slot q, are
+      // decoded 64 at a time as soon as the received words holding them are
+      // complete, so that most items' loads overlap a pass
+      const int g0 = it - gi, avail = (gi + 1) * G::n1;
+      const bool last = gi == G::RMG - 1 || it == nt - 1;
+      if (gi == 0) passes = 0;
+#pragma unroll 1
+      while (passes * 64 < avail && ((passes + 1) * 64 <= avail || last)) {
+        const int f0 = 64 * passes;
+        const int f = f0 + lane < avail ? f0 + lane : avail - 1;
+        const int q = f / G::n1, b = f - q * G::n1;
+        const uint32_t sbyte = rm_decode_block<G::MULT>(lds + G::RB_OFF + q * G::RB + b * G::BSTR);
+        if (f0 + lane < avail) sym[(g0 + q) * G::SSTR + b] = (uint8_t)sbyte;
+        ++passes;
+      }
+      wave_sync();
     }
-    wave_sync();
   }
   // one Reed-Solomon word per lane, or per pair of lanes l, l + 32 when the
   // tile has at most 32 items; lanes past the tile decode a copy of its first
