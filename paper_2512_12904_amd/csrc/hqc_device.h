@@ -190,6 +190,38 @@ __device__ __forceinline__ void build_doubled(uint32_t *u2) {
   wave_sync();
 }
 
+// The same doubled copy written from registers: ur[c] holds dword lane + 64c
+// of a (c < NR, dwords 0 .. DW).  U2[DW + i] takes the bits of dwords i - 1
+// and i of a, the previous dword coming from the next lower lane through a
+// wave-wide DPP shift (lane 0 takes lane 63 of the previous register), so no
+// LDS read is needed.  Called by all 64 lanes; the caller orders these LDS
+// writes before the first read.
+template <int ID, int NR>
+__device__ __forceinline__ void build_doubled_regs(uint32_t *u2, const uint32_t (&ur)[NR]) {
+  using G = Geo<ID>;
+  const int lane = lane_id();
+  constexpr int NC = (G::U2 - G::DW + 63) / 64;
+  static_assert(G::DW / 64 < NR, "the top dword is held");
+  const uint32_t udw = rdlane(ur[G::DW / 64], G::DW % 64) & ((1u << G::NB) - 1u);
+  uint32_t carry = udw << (32 - G::NB);  // makes U2[DW] = udw | a0 << NB
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    uint32_t hi = 0u;
+    if (c < NR) hi = j < G::DW ? ur[c < NR ? c : 0] : (j == G::DW ? udw : 0u);
+    // wave_shr:1 -- lane l reads lane l - 1, lane 0 keeps carry
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)carry, (int)hi, 0x138, 0xF, 0xF, false);
+    const int D = G::DW + j;
+    if (D < G::U2) u2[D] = __builtin_amdgcn_alignbit(hi, lo, 32 - G::NB);
+    carry = rdlane(hi, 63);
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const int d = lane + 64 * c;
+    if (d < G::DW) u2[d] = ur[c];
+  }
+}
+
 // shreg for NIDX support indices held lane-strided in idx[] (index 64c + l in
 // lane l of idx[c]): sh = n - (index mod n) in [1, n]
 template <int ID, int NREG>

@@ -190,16 +190,12 @@ __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *l
   }
   if constexpr (OP == OP_DECODE) return;
 
-  // S0: U2[0 .. DW] = u (dword DW raw for now), then U2[DW ..] = the wrapped
-  // continuation U2[t] = u[t - n]
-#pragma unroll
-  for (int i = 0; i < IR::UREG; ++i) {
-    const int d = lane + 64 * i;
-    if (d <= G::DW) u2[d] = r.u[i];
-  }
+  // S0: U2[0 .. DW) = u, then U2[DW ..] = the wrapped continuation
+  // U2[t] = u[t - n], from the registers
+  build_doubled_regs<ID, IR::UREG>(u2, r.u);
   uint32_t shreg[G::YREG];
   window_shifts<ID, G::YREG>(r.y, shreg);
-  build_doubled<ID>(u2);
+  wave_sync();
 
   // S1: product, R output dwords per lane
   uint32_t acc[G::R];
