@@ -9,8 +9,10 @@
 // One 64-lane wavefront per item (persistent grid).  Dense operands are
 // staged as a bit-level doubled copy in LDS and multiplied by the sparse
 // operand with the windowed product of Eq. (1) shared with decryption.  The
-// sparse addends (x, r1, e) are added as products with the constant
-// polynomial 1, so their secret positions never become memory addresses.
+// product goes to an LDS buffer, where the sparse addends (x, r1, e) are
+// XORed in one bit per index by a single lane (no bank conflicts, so the
+// secret positions do not change the timing), and the buffer is written out
+// (or compared with a received ciphertext) with coalesced stores.
 // The codeword mG: Reed-Solomon parity by a wavefront-wide LFSR (lane j
 // holds register j; GF(2^8) products through the wave-resident log/exp
 // tables), then each output dword of the duplicated RM(1,7) code from its
@@ -73,14 +75,21 @@ __device__ __forceinline__ uint32_t rm_pattern(uint32_t v) {
   return p;
 }
 
-// Stage the dense polynomial a (dwords 0 .. DW of a row) into U2 and make
-// the doubled copy.
+// Load the dense polynomial a (dwords 0 .. DW of a row) into registers and
+// write its bit-level doubled copy to U2.
 template <int ID>
 __device__ __forceinline__ void stage_dense(const uint64_t *row, uint32_t *u2) {
   using G = Geo<ID>;
+  constexpr int NR = (G::DW + 1 + 63) / 64;
   const uint32_t *src = (const uint32_t *)row;
-  for (int d = lane_id(); d <= G::DW; d += 64) u2[d] = src[d];
-  build_doubled<ID>(u2);
+  uint32_t r[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const int d = lane_id() + 64 * c;
+    r[c] = src[d <= G::DW ? d : G::DW];
+  }
+  build_doubled_regs<ID, NR>(u2, r);
+  wave_sync();
 }
 
 template <int NIDX>
@@ -124,42 +133,73 @@ __device__ __forceinline__ void floyd(const uint32_t *a, uint32_t (&p)[(W + 63) 
   }
 }
 
-// a*(support) + 1*(support2) -> acc (all R dwords of every lane); supports
-// held lane-strided in registers
-template <int ID, int N1, int N2>
-__device__ __forceinline__ void two_products(const uint32_t *u2, const uint32_t *one,
-                                             const uint32_t (&i1)[(N1 + 63) / 64],
-                                             const uint32_t (&i2)[(N2 + 63) / 64],
-                                             uint32_t (&acc)[Geo<ID>::R]) {
-  uint32_t s1[(N1 + 63) / 64], s2[(N2 + 63) / 64];
-  window_shifts<ID, (N1 + 63) / 64>(i1, s1);
-  window_shifts<ID, (N2 + 63) / 64>(i2, s2);
+// acc = the lane's R dwords of a * (sum over the support of X^index)
+template <int ID, int N>
+__device__ __forceinline__ void sparse_product(const uint32_t *u2,
+                                               const uint32_t (&idx)[(N + 63) / 64],
+                                               uint32_t (&acc)[Geo<ID>::R]) {
+  uint32_t sh[(N + 63) / 64];
+  window_shifts<ID, (N + 63) / 64>(idx, sh);
 #pragma unroll
   for (int j = 0; j < Geo<ID>::R; ++j) acc[j] = 0;
-  product_acc<ID, N1>(u2, s1, acc);
-  product_acc<ID, N2>(one, s2, acc);
+  product_acc<ID, N>(u2, sh, acc);
 }
 
-// store a full n-bit polynomial (bits >= n cleared) from the lanes' dwords,
-// or (CHECK) return the OR of its differences from the stored row
-template <int ID, bool CHECK>
-__device__ __forceinline__ uint32_t store_full(uint64_t *row, const uint64_t *cmp,
-                                               const uint32_t (&acc)[Geo<ID>::R]) {
-  using G = Geo<ID>;
-  uint32_t *dst = (uint32_t *)row;
-  const uint32_t *src = (const uint32_t *)cmp;
+// buf ^= sum over the support of X^(index mod n), indices >= limit dropped.
+// One lane XORs one bit per index with an LDS atomic; the dword and the bit
+// are selects (a dropped index XORs 0 into dword 0), so every index costs the
+// same, and a single-lane access has no bank conflict that could depend on
+// the address.  This replaces a product with the constant polynomial 1.
+template <int ID, int W>
+__device__ __forceinline__ void sparse_xor(uint32_t *buf, const uint32_t (&p)[(W + 63) / 64],
+                                           uint32_t limit) {
+  constexpr int NR = (W + 63) / 64;
   const int lane = lane_id();
-  uint32_t diff = 0;
+  uint32_t ad[NR], bt[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const uint32_t q = p[c] % (uint32_t)Set<ID>::n;
+    const bool in = q < limit;
+    ad[c] = in ? q >> 5 : 0u;
+    bt[c] = in ? 1u << (q & 31u) : 0u;
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const int cnt = W - 64 * c < 64 ? W - 64 * c : 64;
+#pragma unroll 1
+    for (int l = 0; l < cnt; ++l) {
+      const uint32_t a = rdlane(ad[c], l), b = rdlane(bt[c], l);
+      if (lane == 0) atomicXor(&buf[a], b);
+    }
+  }
+}
+
+// the lane's R product dwords into buf (bits >= n of the last dword cleared)
+template <int ID>
+__device__ __forceinline__ void put_full(uint32_t *buf, const uint32_t (&acc)[Geo<ID>::R]) {
+  using G = Geo<ID>;
+  const int lane = lane_id();
 #pragma unroll
   for (int j = 0; j < G::R; ++j) {
     const int d = lane * G::R + j;
-    if (d < 2 * G::U_WORDS) {
-      uint32_t val = d < G::DW ? acc[j] : (d == G::DW ? acc[j] & ((1u << G::NB) - 1u) : 0u);
-      if constexpr (CHECK)
-        diff |= src[d] ^ val;
-      else
-        dst[d] = val;
-    }
+    if (d <= G::DW) buf[d] = d < G::DW ? acc[j] : acc[j] & ((1u << G::NB) - 1u);
+  }
+}
+
+// the first ndw dwords of buf to a row (lane-strided, coalesced; dwords
+// ndw .. nout - 1 zero), or (CHECK) the OR of their differences from a row
+template <bool CHECK>
+__device__ __forceinline__ uint32_t emit(const uint32_t *buf, int ndw, int nout, uint64_t *row,
+                                         const uint64_t *cmp) {
+  uint32_t *dst = (uint32_t *)row;
+  const uint32_t *src = (const uint32_t *)cmp;
+  uint32_t diff = 0;
+  for (int d = lane_id(); d < nout; d += 64) {
+    const uint32_t val = d < ndw ? buf[d] : 0u;
+    if constexpr (CHECK)
+      diff |= src[d] ^ val;
+    else
+      dst[d] = val;
   }
   return diff;
 }
@@ -170,7 +210,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   using G = Geo<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
-  uint32_t *one = lds + G::U2;
+  uint32_t *buf = lds + G::U2;
   uint8_t *sym = (uint8_t *)(lds + 2 * G::U2);
   uint32_t acc[G::R];
   const size_t nw = (size_t)G::U_WORDS;
@@ -182,8 +222,12 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     load_support<G::w>(a.y + (size_t)item * G::w, iy);
     load_support<G::w>(a.x + (size_t)item * G::w, ix);
     stage_dense<ID>(a.h + item * nw, u2);
-    two_products<ID, G::w, G::w>(u2, one, iy, ix, acc);
-    store_full<ID, false>(a.s_out + item * nw, nullptr, acc);
+    sparse_product<ID, G::w>(u2, iy, acc);
+    put_full<ID>(buf, acc);
+    wave_sync();
+    sparse_xor<ID, G::w>(buf, ix, (uint32_t)G::n);
+    wave_sync();
+    emit<false>(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw, nullptr);
     wave_sync();
     return;
   } else {
@@ -202,8 +246,14 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     }
     // Alg. 1: u = r1 + h*r2
     stage_dense<ID>(a.h + item * nw, u2);
-    two_products<ID, WR, WR>(u2, one, ir2, ir1, acc);
-    uint32_t diff = store_full<ID, CHECK>(a.u_out + item * nw, a.u_in + item * nw, acc);
+    sparse_product<ID, WR>(u2, ir2, acc);
+    put_full<ID>(buf, acc);
+    wave_sync();
+    sparse_xor<ID, WR>(buf, ir1, (uint32_t)G::n);
+    wave_sync();
+    uint32_t diff = emit<CHECK>(buf, G::DW + 1, 2 * G::U_WORDS, a.u_out + item * nw,
+                                a.u_in + item * nw);
+    wave_sync();
 
     // Reed-Solomon parity of m: x^{2d} m(x) mod g(x), register j in lane j
     constexpr int TD = G::TD;
@@ -229,9 +279,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     // v = mG + s*r2 + e, first n1*n2 bits
     wave_sync();
     stage_dense<ID>(a.s + item * nw, u2);
-    two_products<ID, WR, WE>(u2, one, ir2, ie, acc);
-    uint32_t *dst = (uint32_t *)(a.v_out + item * (size_t)G::V_WORDS);
-    const uint32_t *vin = (const uint32_t *)(a.v_in + item * (size_t)G::V_WORDS);
+    sparse_product<ID, WR>(u2, ir2, acc);
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
       const int d = lane * G::R + j;
@@ -241,13 +289,13 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       const uint32_t p = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((c & 31u) << 2), (int)pat);
       const uint32_t flip = ((c >> 7) ^ ((c >> 5) & (uint32_t)w) ^ ((c >> 6) & ((uint32_t)w >> 1))) & 1u;
       const uint32_t word = p ^ (0u - flip);
-      if (d < G::W32) {
-        if constexpr (CHECK)
-          diff |= vin[d] ^ acc[j] ^ word;
-        else
-          dst[d] = acc[j] ^ word;
-      }
+      if (d < G::W32) buf[d] = acc[j] ^ word;
     }
+    wave_sync();
+    sparse_xor<ID, WE>(buf, ie, (uint32_t)(G::n1 * G::n2));
+    wave_sync();
+    diff |= emit<CHECK>(buf, G::W32, G::W32, a.v_out + item * (size_t)G::V_WORDS,
+                        a.v_in + item * (size_t)G::V_WORDS);
     if constexpr (CHECK) {
       const bool same = __ballot(diff != 0u) == 0ull;
       if (lane == 0) a.ok[item] = same ? 1u : 0u;
@@ -264,15 +312,6 @@ __global__ __launch_bounds__(64) void hqc_encrypt_kernel(EncArgs a) {
   const uint32_t exp4 = kGf.exp4[lane];
   const uint32_t log4 = kGf.log4[lane];
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
-  // the doubled copy of the constant polynomial 1: bits 0 and n
-  uint32_t *one = lds + G::U2;
-  for (int d = lane; d < G::U2; d += 64) one[d] = 0;
-  wave_sync();
-  if (lane == 0) {
-    one[0] = 1u;
-    one[G::DW] = 1u << G::NB;
-  }
-  wave_sync();
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
     run_item<ID, MODE>(a, item, lds, exp4, log4, pat);
 }
