@@ -196,6 +196,13 @@ int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint6
  * the caller, overwritten by the call and free again once the stream has
  * passed it.  params->flags must be 0. */
 #define HQC_KEM_KEY_BYTES 32
+/* The KEM's fixed-weight sampling alone: for each item, 2 wr + we draws
+ * (32-bit words; rows of 2 wr + we words) become the supports of r1, r2 and e
+ * (rows of 2 wr + we indices in [0, n), each vector's indices distinct, in
+ * index order i) by Floyd's sampling as above.  draws, supp_out 4-byte
+ * aligned device memory; params->flags must be 0. */
+int hqc_fixed_weight_batch(const hqc_params_t *params, const uint32_t *draws, uint32_t *supp_out,
+                           size_t count);
 /* Workspace size for count items of one parameter set (0 for a bad id). */
 size_t hqc_kem_workspace_bytes(int param_id, size_t count);
 int hqc_kem_encaps_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,

@@ -574,6 +574,28 @@ int kem_check(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
 
 }  // namespace
 
+int hqc_fixed_weight_batch(const hqc_params_t *params, const uint32_t *draws, uint32_t *supp_out,
+                           size_t count) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  if (count == 0) return HQC_OK;
+  const size_t row = hqc::kem_draw_words(params->param_id) * 4;
+  if (!aligned(draws, 4) || !aligned(supp_out, 4) || !in_device_allocation(draws, count * row) ||
+      !in_device_allocation(supp_out, count * row))
+    return HQC_EINVAL;
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.draws = draws;
+  a.draw_stride = hqc::kem_draw_words(params->param_id);
+  a.supp_out = supp_out;
+  a.count = (uint32_t)count;
+  return run_encrypt(hqc::ENC_SAMPLE, params, a);
+}
+
 size_t hqc_kem_workspace_bytes(int param_id, size_t count) {
   KemLayout lay;
   return kem_layout(param_id, count, &lay) ? lay.total : 0;

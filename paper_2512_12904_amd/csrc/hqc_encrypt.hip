@@ -104,31 +104,44 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
 // Floyd's sampling (Bentley & Floyd 1987, positions reflected): W distinct
 // positions in [0, n) from W 32-bit draws a_i.  p_i = i + floor(a_i (n - i)
 // / 2^32); then for i = W-1 down to 0, p_i becomes i if a later p_j equals
-// it.  Position i is kept in lane i mod 64 of p[i / 64]; the loop length and
-// every access are fixed, the replacement is a select.
+// it.  The three vectors of one encryption (r1, r2, e: wr = we in every set)
+// are sampled in one loop, so that their independent sequential steps
+// overlap.  Position i of vector v is in lane i mod 64 of p[v][i / 64]; the
+// loop length and every access are fixed, the replacement is a select.
 template <int ID, int W>
-__device__ __forceinline__ void floyd(const uint32_t *a, uint32_t (&p)[(W + 63) / 64]) {
+__device__ __forceinline__ void floyd3(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
   constexpr int NR = (W + 63) / 64;
   constexpr uint32_t n = (uint32_t)Set<ID>::n;
   const int lane = lane_id();
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
-    const int i = 64 * c + lane;
-    const uint32_t ai = a[i < W ? i : 0];
-    p[c] = i < W ? (uint32_t)i + __umulhi(ai, n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
-  }
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const int i = 64 * c + lane;
+      const uint32_t ai = a[v * W + (i < W ? i : 0)];
+      p[v][c] = i < W ? (uint32_t)i + __umulhi(ai, n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
+    }
 #pragma unroll
   for (int c = NR - 1; c >= 0; --c) {
     const int top = W - 64 * c < 64 ? W - 64 * c : 64;
 #pragma unroll 1
     for (int l = top - 1; l >= 0; --l) {
       const int i = 64 * c + l;
-      const uint32_t pi = rdlane(p[c], l);
-      bool hit = false;
+      uint32_t pi[3];
+      bool hit[3] = {false, false, false};
 #pragma unroll
-      for (int c2 = c; c2 < NR; ++c2) hit |= (64 * c2 + lane > i) && p[c2] == pi;
-      const bool dup = __ballot(hit) != 0ull;
-      p[c] = (dup && lane == l) ? (uint32_t)i : p[c];
+      for (int v = 0; v < 3; ++v) pi[v] = rdlane(p[v][c], l);
+#pragma unroll
+      for (int c2 = c; c2 < NR; ++c2) {
+        const bool later = 64 * c2 + lane > i;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) hit[v] |= later && p[v][c2] == pi[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const bool dup = __ballot(hit[v]) != 0ull;
+        p[v][c] = (dup && lane == l) ? (uint32_t)i : p[v][c];
+      }
     }
   }
 }
@@ -215,7 +228,28 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   uint32_t acc[G::R];
   const size_t nw = (size_t)G::U_WORDS;
 
-  if constexpr (MODE == ENC_KEYGEN) {
+  if constexpr (MODE == ENC_SAMPLE) {
+    constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
+    static_assert(WR == WE, "one sampling loop for r1, r2 and e");
+    uint32_t sp[3][(WR + 63) / 64];
+    floyd3<ID, WR>(a.draws + (size_t)item * a.draw_stride, sp);
+    const auto &ir1 = sp[0], &ir2 = sp[1], &ie = sp[2];
+    uint32_t *out = a.supp_out + (size_t)item * (2 * WR + WE);
+#pragma unroll
+    for (int c = 0; c < (WR + 63) / 64; ++c) {
+      const int i = 64 * c + lane;
+      if (i < WR) {
+        out[i] = ir1[c];
+        out[WR + i] = ir2[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < (WE + 63) / 64; ++c) {
+      const int i = 64 * c + lane;
+      if (i < WE) out[2 * WR + i] = ie[c];
+    }
+    return;
+  } else if constexpr (MODE == ENC_KEYGEN) {
     // Alg. 3: s = x + h*y
     constexpr int NR = (G::w + 63) / 64;
     uint32_t iy[NR], ix[NR];
@@ -233,16 +267,15 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   } else {
     constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
     constexpr bool CHECK = MODE == ENC_CHECK;
-    uint32_t ir1[(WR + 63) / 64], ir2[(WR + 63) / 64], ie[(WE + 63) / 64];
+    static_assert(WR == WE, "one sampling loop for r1, r2 and e");
+    uint32_t sp[3][(WR + 63) / 64];
+    auto &ir1 = sp[0], &ir2 = sp[1], &ie = sp[2];
     if constexpr (MODE == ENC_ARRAYS) {
       load_support<WR>(a.r1 + (size_t)item * WR, ir1);
       load_support<WR>(a.r2 + (size_t)item * WR, ir2);
       load_support<WE>(a.e + (size_t)item * WE, ie);
     } else {
-      const uint32_t *dr = a.draws + (size_t)item * a.draw_stride;
-      floyd<ID, WR>(dr, ir1);
-      floyd<ID, WR>(dr + WR, ir2);
-      floyd<ID, WE>(dr + 2 * WR, ie);
+      floyd3<ID, WR>(a.draws + (size_t)item * a.draw_stride, sp);
     }
     // Alg. 1: u = r1 + h*r2
     stage_dense<ID>(a.h + item * nw, u2);
@@ -336,6 +369,7 @@ const void *encrypt_kernel_ptr(int mode, int pid) {
     case ENC_KEYGEN: return enc_ptr<ENC_KEYGEN>(pid);
     case ENC_ARRAYS: return enc_ptr<ENC_ARRAYS>(pid);
     case ENC_STREAM: return enc_ptr<ENC_STREAM>(pid);
+    case ENC_SAMPLE: return enc_ptr<ENC_SAMPLE>(pid);
     default: return enc_ptr<ENC_CHECK>(pid);
   }
 }

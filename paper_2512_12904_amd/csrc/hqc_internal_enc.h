@@ -12,8 +12,9 @@ namespace hqc {
 // The supports come from arrays (ENC_ARRAYS) or are sampled from a row of
 // 32-bit draws (ENC_STREAM, ENC_CHECK: Floyd's sampling, wr, wr, we draws);
 // ENC_CHECK compares the result with (u_in, v_in) instead of storing it and
-// writes ok[item] = 1 when every word is equal, else 0.
-enum EncMode : int { ENC_KEYGEN = 0, ENC_ARRAYS = 1, ENC_STREAM = 2, ENC_CHECK = 3 };
+// writes ok[item] = 1 when every word is equal, else 0.  ENC_SAMPLE only
+// samples the supports from the draws and stores them.
+enum EncMode : int { ENC_KEYGEN = 0, ENC_ARRAYS = 1, ENC_STREAM = 2, ENC_CHECK = 3, ENC_SAMPLE = 4 };
 struct EncArgs {
   const uint64_t *h, *s;
   const uint32_t *x, *y;
@@ -23,6 +24,7 @@ struct EncArgs {
   const uint64_t *u_in, *v_in;  // ENC_CHECK
   uint64_t *s_out, *u_out, *v_out;
   uint32_t *ok;                 // ENC_CHECK
+  uint32_t *supp_out;           // ENC_SAMPLE: rows of 2 wr + we indices (r1, r2, e)
   uint32_t draw_stride;
   uint32_t count;
 };

@@ -30,7 +30,7 @@ EXPORTS = (
     "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
     "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
-    "hqc_kem_decaps_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
+    "hqc_kem_decaps_batch", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
     "hqc_ring_mul_batch",
 )
 
@@ -96,6 +96,7 @@ def lib():
                                            sz]
         L.hqc_kem_decaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp,
                                            sz, sz]
+        L.hqc_fixed_weight_batch.argtypes = [ctypes.POINTER(Params), vp, vp, sz]
         L.hqc_ring_workspace_bytes.restype = ctypes.c_size_t
         L.hqc_ring_workspace_bytes.argtypes = [ctypes.c_int, sz, sz]
         L.hqc_ring_default_threshold.restype = ctypes.c_uint32
@@ -424,3 +425,18 @@ def ring_mul_batch(pid, a, b, out=None, threshold=None, path_out=None, workspace
         _dev(workspace, torch.uint8, "workspace"), workspace.numel(), count)
     _check(rc, "hqc_ring_mul_batch")
     return out, path_out
+
+
+def fixed_weight_batch(pid, draws, out=None, grid=0, stream=None):
+    """Floyd's sampling of the KEM: draws (count x (2 wr + we) int32) ->
+    supports of r1, r2, e (same shape)."""
+    sz = sizes(pid)
+    nd = 2 * sz["wr"] + sz["we"]
+    count = draws.shape[0]
+    if out is None:
+        out = torch.empty((count, nd), dtype=torch.int32, device=draws.device)
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_fixed_weight_batch(ctypes.byref(p), _dev(draws, torch.int32, "draws", (count, nd)),
+                                      _dev(out, torch.int32, "out", (count, nd)), count)
+    _check(rc, "hqc_fixed_weight_batch")
+    return out

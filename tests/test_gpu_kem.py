@@ -129,3 +129,38 @@ def test_workspace_too_small_is_rejected(hqc):
         ctypes.byref(prm), vp(hd.data_ptr()), vp(sd.data_ptr()), vp(md.data_ptr()),
         vp(u.data_ptr()), vp(v.data_ptr()), vp(key.data_ptr()), vp(big.data_ptr()), need - 1, 4)
     assert rc == hqc.HQC_EINVAL
+
+
+def _draw_for(n, i, t):
+    # the smallest 32-bit draw with i + floor(a (n - i) / 2^32) = i + t
+    return -(-(t << 32) // (n - i))
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_fixed_weight_sampling_edge_draws(hqc, pid):
+    # crafted draws: no collision, every draw maximal (a chain of collisions),
+    # a position equal to the index of a replaced later position, and random
+    say("case: Floyd sampling pid=%d" % pid)
+    p = datasets.sizes(pid)
+    n, wr, we = p["n"], p["wr"], p["we"]
+    nd = 2 * wr + we
+    rows = [np.zeros(nd, np.uint32), np.full(nd, 0xFFFFFFFF, np.uint32)]
+    r = np.zeros(nd, np.uint32)
+    for off, w in ((0, wr), (wr, wr), (2 * wr, we)):
+        P = w + 107
+        t = {w - 1: P - (w - 1), w - 2: P - (w - 2)}   # p = P twice: w-2 is replaced
+        t[3] = (w - 2) - 3                             # p_3 = w - 2: hits the replaced index
+        t[1] = (w - 1) - 1                             # p_1 = w - 1: index of a kept position
+        for i in range(w):
+            r[off + i] = _draw_for(n, i, t.get(i, 0) if i in t else 50 + 3 * i)
+    rows.append(r)
+    rows.append(synth.words(0x7E57 + pid, (nd + 1) // 2).view(np.uint32)[:nd])
+    draws = np.stack(rows)
+    import torch
+    out = hqc.fixed_weight_batch(pid, dev(draws))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for k, d in enumerate(draws):
+        ref = np.concatenate([oracle.fixed_weight(n, wr, d[:wr]), oracle.fixed_weight(n, wr, d[wr:2 * wr]),
+                              oracle.fixed_weight(n, we, d[2 * wr:])])
+        assert (got[k] == ref).all(), k
