@@ -40,7 +40,6 @@ template <int ID> struct Geo {
   static constexpr int U2 = 64 * R + DW + 2;         // doubled-u dwords (covers every window)
   static constexpr int RB = n1 * BSTR;               // received-word dwords
   static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
-  static constexpr int SYMREG = (n1 + 63) / 64;      // blocks per lane
   // Reed-Solomon scratch per lane (uint16 entries): reversed log-syndromes
   // (2 TD entries, zero-padded) then the error evaluator's logs (TD entries)
   static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 3 * TD);
@@ -56,6 +55,9 @@ template <int ID> struct Geo {
   // HQC-1 keeps the received words of RMG = 4 items and RM-decodes their
   // 4 x 46 = 184 blocks in 3 passes of 64 lanes instead of 4 passes of 46
   static constexpr int RMG = ID == 1 ? 4 : 1;
+  // HQC-5 decodes each RM block on a lane pair: its 90 blocks take 3 passes
+  // of 32 pairs (1.5 full passes) instead of 2 passes of 64 lanes
+  static constexpr bool PAIR_RM = ID == 5;
   static constexpr int A_BYTES =
       (cmax(4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB), TROWS * RS_BYTES_LANE) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;

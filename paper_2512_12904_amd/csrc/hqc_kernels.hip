@@ -124,6 +124,127 @@ __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
   return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
 }
 
+// ---- S3-S5: one duplicated RM(1,7) block -> symbol byte, on a lane pair -------
+// Lanes l and l + 32 decode the same block.  Half s = l / 32 takes positions
+// 32s .. 32s+31 and 64+32s .. 64+32s+31 (dwords s and 2+s of every copy):
+// its 32 registers h[m'] hold (F(m), F(m+64)) for m = 32s + m'.  The
+// transform stages pairing m with m + 1 .. m + 16 and m with m + 64 are
+// local; the stage pairing m with m + 32 pairs the halves and goes through
+// v_permlane32_swap_b32 (the stages commute, so it runs last).  Both lanes
+// return the symbol.
+template <int MULT>
+__device__ __forceinline__ uint32_t rm_decode_pair(const uint32_t *blk) {
+  const bool upper = lane_id() >= 32;
+  const int s = upper ? 1 : 0;
+  // bit-sliced count of set copies per position: F = p0 + 2 p1 + 4 p2, for
+  // the half's two dwords e = 0, 1 (dword s + 2e of each copy)
+  uint32_t p0[2], p1[2], p2[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const uint32_t *b = blk + 2 * e + s;
+    const uint32_t x = b[0], y = b[4], z = b[8];
+    const uint32_t sm = xor3(x, y, z), cy = maj3(x, y, z);
+    if constexpr (MULT == 3) {
+      p0[e] = sm;
+      p1[e] = cy;
+      p2[e] = 0;
+    } else {
+      const uint32_t d = b[12], f = b[16];
+      const uint32_t sm2 = xor3(sm, d, f), cy2 = maj3(sm, d, f);
+      p0[e] = sm2;
+      p1[e] = cy ^ cy2;
+      p2[e] = cy & cy2;
+    }
+  }
+  // F as bytes, 4 positions per dword: B[g] byte c = F of local position
+  // 4g + c (g < 8: dword e = 0, g >= 8: e = 1).  A nibble of a plane spreads
+  // to the low bit of 4 bytes by one multiply.
+  uint32_t B[16];
+#pragma unroll
+  for (int g = 0; g < 16; ++g) {
+    const int e = g >> 3, sh = 4 * (g & 7);
+    uint32_t v = (__builtin_amdgcn_ubfe(p0[e], sh, 4) * 0x204081u) & 0x01010101u;
+    v += ((__builtin_amdgcn_ubfe(p1[e], sh, 4) * 0x204081u) & 0x01010101u) << 1;
+    if constexpr (MULT == 5) v += ((__builtin_amdgcn_ubfe(p2[e], sh, 4) * 0x204081u) & 0x01010101u) << 2;
+    B[g] = v;
+  }
+  // h[m'] = (F(m), F(m + 64)) as 16-bit halves
+  s16x2 h[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const uint32_t c = (uint32_t)(m & 3);
+    const uint32_t sel = c | 0x0C00u | ((4u + c) << 16) | 0x0C000000u;
+    h[m] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(B[(m >> 2) + 8], B[m >> 2], sel));
+  }
+  // local stages: pairs m', m' + hh inside the half ...
+#pragma unroll
+  for (int hh = 1; hh < 32; hh <<= 1) {
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      if (m & hh) continue;
+      s16x2 a = h[m], c = h[m + hh];
+      h[m] = a + c;
+      h[m + hh] = a - c;
+    }
+  }
+  // ... (F(m), F(m+64)) -> (a + b, a - b) as one v_pk_mad_i16: low = a*1 + b,
+  // high = b*(-1) + a ...
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    uint32_t x = __builtin_bit_cast(uint32_t, h[m]), d;
+    asm("v_pk_mad_i16 %0, %1, %2, %1 op_sel:[0,0,1] op_sel_hi:[1,1,0]"
+        : "=v"(d)
+        : "v"(x), "v"(0xFFFF0001u));
+    h[m] = __builtin_bit_cast(s16x2, d);
+  }
+  // ... and across the halves (the lower half keeps a + b, the upper a - b),
+  // two registers at a time: the first swap gives the lower half both
+  // copies of h[m'] and the upper half both copies of h[m' + 16], each half
+  // forms the sum and the difference, and the second swap returns them
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, h[m]),
+                                                    __builtin_bit_cast(uint32_t, h[m + 16]),
+                                                    false, false);
+    const s16x2 a = __builtin_bit_cast(s16x2, (uint32_t)r[0]);
+    const s16x2 b = __builtin_bit_cast(s16x2, (uint32_t)r[1]);
+    const s16x2 sum = a + b, dif = a - b;
+    const auto t = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, sum),
+                                                    __builtin_bit_cast(uint32_t, dif), false, false);
+    h[m] = __builtin_bit_cast(s16x2, (uint32_t)t[0]);
+    h[m + 16] = __builtin_bit_cast(s16x2, (uint32_t)t[1]);
+  }
+  // H = transform of the counts.  The correlation with codeword (u, sign) is
+  // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u) with H'(0) = H(0) - 64*MULT,
+  // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
+  // One 16-bit key per u: bits 15..8 = |H'(u)| (<= 192 for MULT 3) or
+  // |H'(u)| >> 1 (<= 160 for MULT 5; every H'(u) has the parity of sum F, so
+  // halving keeps the order), bits 7..1 = 127 - u, bit 0 = [H'(u) > 0].
+  h[0].x = (short)(h[0].x - (upper ? 0 : 64 * MULT));
+  // register m' holds u = 32s + m' (low half) and u = 32s + m' + 64 (high);
+  // the keys carry 127 - m' and 63 - m', and the upper half's maximum drops
+  // 2 * 32 from both index fields afterwards (no borrow: the fields are >= 64)
+  u16x2 kmax = {0, 0};
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const uint32_t idx = (uint32_t)(127 - m) << 1 | (uint32_t)(63 - m) << 17;
+    const s16x2 zero = {0, 0};
+    const s16x2 neg = zero - h[m];
+    const s16x2 mag = __builtin_elementwise_max(h[m], neg);
+    const u16x2 sg = __builtin_bit_cast(u16x2, neg) >> (unsigned short)15;  // [H' > 0]
+    const uint32_t mw = __builtin_bit_cast(uint32_t, mag);
+    const uint32_t hiw = MULT == 3 ? mw << 8 : (mw << 7) & 0xFF00FF00u;
+    const uint32_t key = hiw | __builtin_bit_cast(uint32_t, sg) | idx;
+    kmax = __builtin_elementwise_max(kmax, __builtin_bit_cast(u16x2, key));
+  }
+  const u16x2 drop = upper ? u16x2{64, 64} : u16x2{0, 0};
+  kmax = kmax - drop;
+  const uint32_t mine = kmax.x > kmax.y ? kmax.x : kmax.y;
+  const Halves both = halves(mine);
+  const uint32_t best = both.lo > both.hi ? both.lo : both.hi;
+  return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
+}
+
 // ---- S0-S2: received word r = v + (u*y)|_{n1 n2} into the padded rows -------
 
 // One item's inputs, loaded lane-strided into VGPRs ahead of use so that the
@@ -529,30 +650,27 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
                           (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS));
     wave_sync();
     if (!G::COMPACT && it + 1 < nt) prefetch<ID, OP>(sg, cur + 1, regs);
-    if constexpr (G::RMG == 1) {
-      const uint32_t *rb = lds + G::RB_OFF;
-#pragma unroll
-      for (int pass = 0; pass < G::SYMREG; ++pass) {
-        const int j = lane + 64 * pass;
-        const int jj = j < G::n1 ? j : G::n1 - 1;
-        const uint32_t sbyte = rm_decode_block<G::MULT>(rb + jj * G::BSTR);
-        if (j < G::n1) sym[it * G::SSTR + j] = (uint8_t)sbyte;
-      }
-      wave_sync();
-    } else {
+    {
       // the group's blocks, flat index q n1 + b for block b of slot q, are
-      // decoded 64 at a time as soon as the received words holding them are
-      // complete, so that most items' loads overlap a pass
+      // decoded BPP at a time (one lane or one lane pair each) as soon as the
+      // received words holding them are complete, so that most items' loads
+      // overlap a pass
+      constexpr int BPP = G::PAIR_RM ? 32 : 64;
       const int g0 = it - gi, avail = (gi + 1) * G::n1;
       const bool last = gi == G::RMG - 1 || it == nt - 1;
       if (gi == 0) passes = 0;
 #pragma unroll 1
-      while (passes * 64 < avail && ((passes + 1) * 64 <= avail || last)) {
-        const int f0 = 64 * passes;
-        const int f = f0 + lane < avail ? f0 + lane : avail - 1;
+      while (passes * BPP < avail && ((passes + 1) * BPP <= avail || last)) {
+        const int f0 = BPP * passes, fl = f0 + (G::PAIR_RM ? (lane & 31) : lane);
+        const int f = fl < avail ? fl : avail - 1;
         const int q = f / G::n1, b = f - q * G::n1;
-        const uint32_t sbyte = rm_decode_block<G::MULT>(lds + G::RB_OFF + q * G::RB + b * G::BSTR);
-        if (f0 + lane < avail) sym[(g0 + q) * G::SSTR + b] = (uint8_t)sbyte;
+        const uint32_t *blk = lds + G::RB_OFF + q * G::RB + b * G::BSTR;
+        uint32_t sbyte;
+        if constexpr (G::PAIR_RM)
+          sbyte = rm_decode_pair<G::MULT>(blk);
+        else
+          sbyte = rm_decode_block<G::MULT>(blk);
+        if (fl < avail && lane < BPP) sym[(g0 + q) * G::SSTR + b] = (uint8_t)sbyte;
         ++passes;
       }
       wave_sync();
