@@ -158,6 +158,30 @@ def ring_sweep(hqc, pid, count, device, weights=(75, 256, 512, 1024, 2048, 3072,
             "default_threshold": hqc.ring_default_threshold(pid)}
 
 
+def ct_classes(hqc, pid, count, device, reps=3):
+    """Decryption launches of two input classes for counter comparison:
+    class A (one fixed key, u = 0 and v = 0, the codeword of m = 0: the
+    decoder sees no error) then class B (random keys, uniform u and v: every
+    word is past the decoding radius), reps launches each, A first."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    s = dict(SETS[pid])
+    U, V = (s["n"] + 63) // 64, s["n1"] * s["n2"] // 64
+    y = synth.keys(0xC7A + pid, pid, s, 1)[2]
+    uA = torch.zeros((count, U), dtype=torch.int64, device=device)
+    vA = torch.zeros((count, V), dtype=torch.int64, device=device)
+    yA = torch.from_numpy(np.repeat(y, count, axis=0).view(np.int32)).to(device)
+    yB = torch.from_numpy(synth.keys(0xC7B + pid, pid, s, count)[2].view(np.int32)).to(device)
+    uB = torch.from_numpy(synth.words(0xC7C + pid, (count, U)).view(np.int64)).to(device)
+    vB = torch.from_numpy(synth.words(0xC7D + pid, (count, V)).view(np.int64)).to(device)
+    out = torch.empty((count, s["k"]), dtype=torch.uint8, device=device)
+    for args in [(uA, vA, yA)] * reps + [(uB, vB, yB)] * reps:
+        hqc.decrypt_batch(pid, *args, out=out)
+    torch.cuda.synchronize()
+    return {"class_a_launches": reps, "class_b_launches": reps, "items": count}
+
+
 def time_batched(hqc, pid, u, v, y, out, steps, warmup):
     """Per-launch device times (ms) from HIP events on the launch stream."""
     import torch
@@ -321,6 +345,9 @@ def main():
     ap.add_argument("--ring-sweep", type=int, default=0, metavar="ITEMS",
                     help="only time the adaptive ring multiplication's two paths over "
                          "first-operand weights (ITEMS items per set) and print them")
+    ap.add_argument("--ct-classes", type=int, default=0, metavar="REPS",
+                    help="only run REPS decryption launches of a zero-error fixed-key class "
+                         "then REPS of a random class (for counter comparison) and exit")
     ap.add_argument("--no-kem", action="store_true",
                     help="skip the KEM encapsulation / decapsulation timing")
     ap.add_argument("--serving-seconds", type=float, default=2.0)
@@ -344,6 +371,11 @@ def main():
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy, dev)
     sets = [int(x) for x in args.sets.split(",")]
+    if args.ct_classes:
+        print(json.dumps({"ct_classes": {"HQC-%d" % pid: ct_classes(hqc, pid, args.count, dev,
+                                                                    args.ct_classes)
+                                         for pid in sets}}), flush=True)
+        return
     if args.ring_sweep:
         print(json.dumps({"ring_sweep": {"HQC-%d" % pid: ring_sweep(hqc, pid, args.ring_sweep, dev)
                                          for pid in sets}}), flush=True)

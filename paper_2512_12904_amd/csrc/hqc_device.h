@@ -41,8 +41,8 @@ template <int ID> struct Geo {
   static constexpr int RB = n1 * BSTR;               // received-word dwords
   static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
   // Reed-Solomon scratch per lane (uint16 entries): reversed log-syndromes
-  // (2 TD entries, zero-padded) then the error evaluator's logs (TD entries)
-  static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 3 * TD);
+  // (2 TD entries, zero-padded)
+  static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 2 * TD);
   static constexpr int RS_STR = RS_BYTES_LANE / 2;   // in uint16 entries
   static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
   // HQC-5 runs a tile as sub-tiles of at most 32 items (two lanes per
@@ -69,9 +69,15 @@ template <int ID> struct Geo {
 };
 
 // ---- GF(2^8) tables, x^8 + x^4 + x^3 + x^2 + 1, alpha = x ------------------
+// A 256-byte table is held in lanes 0 .. 31, 8 bytes per lane (lo: bytes
+// 8l .. 8l+3, hi: 8l+4 .. 8l+7; lanes 32 .. 63 hold a copy).  A lookup
+// reads source lane idx / 8 of both registers through the LDS crossbar
+// (ds_bpermute_b32): every source lane is below 32, so two lanes reading
+// different entries never meet in one bank and the lookup's timing does not
+// depend on the secret index.
 struct GfTables {
-  uint32_t exp4[64];  // bytes exp[4l .. 4l+3]; exp[255] = exp[0] = 1
-  uint32_t log4[64];  // bytes log[4l .. 4l+3]; log[0] = 0 (callers mark zero)
+  uint32_t exp_lo[32], exp_hi[32];  // exp[i] = alpha^i, exp[255] = exp[0] = 1
+  uint32_t log_lo[32], log_hi[32];  // log[0] = 0 (callers mark zero)
 };
 
 constexpr GfTables make_gf_tables() {
@@ -85,16 +91,23 @@ constexpr GfTables make_gf_tables() {
     if (x & 0x100u) x ^= 0x11Du;
   }
   e[255] = 1;
-  for (int i = 0; i < 64; ++i) {
-    t.exp4[i] = (uint32_t)e[4 * i] | (uint32_t)e[4 * i + 1] << 8 | (uint32_t)e[4 * i + 2] << 16 |
-                (uint32_t)e[4 * i + 3] << 24;
-    t.log4[i] = (uint32_t)l[4 * i] | (uint32_t)l[4 * i + 1] << 8 | (uint32_t)l[4 * i + 2] << 16 |
-                (uint32_t)l[4 * i + 3] << 24;
+  auto word = [](const uint8_t *b) {
+    return (uint32_t)b[0] | (uint32_t)b[1] << 8 | (uint32_t)b[2] << 16 | (uint32_t)b[3] << 24;
+  };
+  for (int i = 0; i < 32; ++i) {
+    t.exp_lo[i] = word(e + 8 * i);
+    t.exp_hi[i] = word(e + 8 * i + 4);
+    t.log_lo[i] = word(l + 8 * i);
+    t.log_hi[i] = word(l + 8 * i + 4);
   }
   return t;
 }
 
 __constant__ GfTables kGf = make_gf_tables();
+
+struct GfTab {
+  uint32_t lo, hi;
+};
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -115,12 +128,22 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Byte idx (0..255) of a table spread over the wave, 4 bytes per lane, read
-// through the LDS crossbar (ds_bpermute_b32 selects lane idx >> 2).  Must run
-// with all 64 lanes active.  width 8 returns the byte, width 0 returns 0.
-__device__ __forceinline__ uint32_t tab(uint32_t table4, uint32_t idx, uint32_t width = 8) {
-  uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)idx, (int)table4);
-  return __builtin_amdgcn_ubfe(w, idx << 3, width);
+// Byte idx (0..255) of a table held as above.  Must run with all 64 lanes
+// active.  width 8 returns the byte, width 0 returns 0.
+__device__ __forceinline__ uint32_t tab(GfTab t, uint32_t idx, uint32_t width = 8) {
+  const int src = (int)((idx >> 1) & 0x7Cu);  // byte address of lane (idx / 8) mod 32
+  const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)t.lo);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)t.hi);
+  return __builtin_amdgcn_ubfe((idx & 4u) ? b : a, (idx & 3u) << 3, width);
+}
+
+__device__ __forceinline__ GfTab gf_exp_tab() {
+  const int l = lane_id() & 31;
+  return {kGf.exp_lo[l], kGf.exp_hi[l]};
+}
+__device__ __forceinline__ GfTab gf_log_tab() {
+  const int l = lane_id() & 31;
+  return {kGf.log_lo[l], kGf.log_hi[l]};
 }
 
 // s mod 255 for s in [0, 509] (as an exp index in [0, 254])
@@ -130,12 +153,12 @@ __device__ __forceinline__ uint32_t red255(uint32_t s) {
 }
 
 // log with zero marked: log(x), or ZL (+ log[0]) when x == 0
-__device__ __forceinline__ uint32_t logz(uint32_t log4, uint32_t x) {
+__device__ __forceinline__ uint32_t logz(GfTab log4, uint32_t x) {
   return tab(log4, x) | (x == 0 ? ZL : 0u);
 }
 
 // alpha^s for a sum of logs s (0 when s carries a zero mark)
-__device__ __forceinline__ uint32_t expz(uint32_t exp4, uint32_t s) {
+__device__ __forceinline__ uint32_t expz(GfTab exp4, uint32_t s) {
   uint32_t v = tab(exp4, red255(s) & 0xFFu);
   return s < 512u ? v : 0u;
 }

@@ -219,7 +219,7 @@ __device__ __forceinline__ uint32_t emit(const uint32_t *buf, int ndw, int nout,
 
 template <int ID, int MODE>
 __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32_t *lds,
-                                         uint32_t exp4, uint32_t log4, uint32_t pat) {
+                                         GfTab exp4, GfTab log4, uint32_t pat) {
   using G = Geo<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
@@ -342,8 +342,8 @@ __global__ __launch_bounds__(64) void hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
-  const uint32_t exp4 = kGf.exp4[lane];
-  const uint32_t log4 = kGf.log4[lane];
+  const GfTab exp4 = gf_exp_tab();
+  const GfTab log4 = gf_log_tab();
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
     run_item<ID, MODE>(a, item, lds, exp4, log4, pat);

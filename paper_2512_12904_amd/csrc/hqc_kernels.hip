@@ -346,48 +346,138 @@ __device__ __forceinline__ void received_word(const ItemRegs<ID> &r, uint32_t *l
   }
 }
 
+// ---- GF(2)-linear steps of S6 and S8-S10 as bit rows -------------------------
+// A sum of the word's bytes times fixed field elements is GF(2)-linear in the
+// bits of those bytes: it is the XOR of one fixed row per set bit, row (j, b)
+// being alpha^b times the constants that byte j is multiplied by.  The rows
+// are the same for every lane, so they are read into scalar registers; each
+// bit becomes an all-ones or all-zero mask that selects its row.  The
+// syndromes and the Chien / Forney evaluations thus read no table at a
+// word-dependent index and cost two VALU operations per bit and dword of
+// results.
+template <int NR, int Q> struct BitRows {
+  uint32_t r[NR][8][Q];
+};
+
+struct GfPow {
+  uint8_t e[255];
+};
+constexpr GfPow make_gf_pow() {
+  GfPow t{};
+  unsigned x = 1;
+  for (int i = 0; i < 255; ++i) {
+    t.e[i] = (uint8_t)x;
+    x <<= 1;
+    if (x & 0x100u) x ^= 0x11Du;
+  }
+  return t;
+}
+
+// syndrome rows: byte t of dword q of row (j, b) is alpha^(b + i j) for the
+// syndrome index i = 4q + t + 1 <= NS.  HQC-1 and HQC-3 keep all 2 delta
+// syndromes (one lane per word computes them all, a lane pair uses the
+// first delta); HQC-5 always decodes on lane pairs and keeps delta.
+template <int ID> struct SynShape {
+  static constexpr int NS = ID == 5 ? Geo<ID>::TD / 2 : Geo<ID>::TD;
+  static constexpr int Q = (NS + 3) / 4;
+  using T = BitRows<Geo<ID>::n1, Q>;
+};
+template <int ID> constexpr typename SynShape<ID>::T make_syn_rows() {
+  using Sh = SynShape<ID>;
+  typename Sh::T t{};
+  const GfPow g = make_gf_pow();
+  for (int j = 0; j < Geo<ID>::n1; ++j)
+    for (int b = 0; b < 8; ++b)
+      for (int q = 0; q < Sh::Q; ++q) {
+        uint32_t w = 0;
+        for (int u = 0; u < 4; ++u) {
+          const int i = 4 * q + u + 1;
+          if (i <= Sh::NS) w |= (uint32_t)g.e[(b + i * j) % 255] << (8 * u);
+        }
+        t.r[j][b][q] = w;
+      }
+  return t;
+}
+
+// evaluation rows at the message positions X = alpha^(TD + t), t < k: byte u
+// of dword p of row (e, b) is alpha^(b - e (TD + 4p + u)), the factor of bit
+// b of coefficient e of Lambda or Omega in its value at X^-1
+template <int ID> struct EvalShape {
+  static constexpr int P = Geo<ID>::k / 4;
+  using T = BitRows<Geo<ID>::TD + 1, P>;
+};
+template <int ID> constexpr typename EvalShape<ID>::T make_eval_rows() {
+  using G = Geo<ID>;
+  typename EvalShape<ID>::T t{};
+  const GfPow g = make_gf_pow();
+  for (int e = 0; e <= G::TD; ++e)
+    for (int b = 0; b < 8; ++b)
+      for (int p = 0; p < EvalShape<ID>::P; ++p) {
+        uint32_t w = 0;
+        for (int u = 0; u < 4; ++u) {
+          const int j = G::TD + 4 * p + u;
+          w |= (uint32_t)g.e[((b - e * j) % 255 + 255) % 255] << (8 * u);
+        }
+        t.r[e][b][p] = w;
+      }
+  return t;
+}
+
+__constant__ SynShape<1>::T kSyn1 = make_syn_rows<1>();
+__constant__ SynShape<3>::T kSyn3 = make_syn_rows<3>();
+__constant__ SynShape<5>::T kSyn5 = make_syn_rows<5>();
+__constant__ EvalShape<1>::T kEval1 = make_eval_rows<1>();
+__constant__ EvalShape<3>::T kEval3 = make_eval_rows<3>();
+__constant__ EvalShape<5>::T kEval5 = make_eval_rows<5>();
+
+template <int ID> __device__ __forceinline__ const typename SynShape<ID>::T &syn_rows() {
+  if constexpr (ID == 1) return kSyn1;
+  else if constexpr (ID == 3) return kSyn3;
+  else return kSyn5;
+}
+template <int ID> __device__ __forceinline__ const typename EvalShape<ID>::T &eval_rows() {
+  if constexpr (ID == 1) return kEval1;
+  else if constexpr (ID == 3) return kEval3;
+  else return kEval5;
+}
+
+// acc[q] ^= rows[b][q] for every set bit b of the byte x, q < NQ
+template <int NQ, int Q>
+__device__ __forceinline__ void add_rows(uint32_t (&acc)[NQ], uint32_t x,
+                                         const uint32_t (&rows)[8][Q]) {
+  static_assert(NQ <= Q, "rows cover the accumulators");
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1);
+    // v_bitop3 truth table 0x6C: S1 ^ (S0 & S2)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = __builtin_amdgcn_bitop3_b32(rows[b][q], acc[q], m, 0x6C);
+  }
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint32_t *a, int t) {
+  return __builtin_amdgcn_ubfe(a[t >> 2], 8 * (t & 3), 8);
+}
+
 // ---- S6-S10: Reed-Solomon decode of one item per lane ------------------------
 template <int ID, int OP>
 __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, uint16_t *my, uint32_t exp4,
-                                        uint32_t log4) {
+                                        const uint8_t *cs, uint16_t *my, GfTab exp4,
+                                        GfTab log4) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
+  constexpr int P = EvalShape<ID>::P;
 
-  // S6: S_i = sum_j c_j alpha^(i j), in groups of SG syndromes so that only
-  // SG accumulators and SG table reads are in flight; within a group the
-  // exponent log c_j + i j steps by j per syndrome
-  constexpr int SG = 10;
-  uint32_t S[TD];
+  // S6: S_i = sum_j c_j alpha^(i j), i = 1 .. TD; byte i - 1 of sa (four to
+  // a dword) is S_i
+  uint32_t sa[SynShape<ID>::Q];
 #pragma unroll
-  for (int g0 = 0; g0 < TD; g0 += SG) {
-    const int gn = TD - g0 < SG ? TD - g0 : SG;
-    uint32_t acc[SG];
-#pragma unroll
-    for (int i = 0; i < SG; ++i) acc[i] = 0;
-    uint32_t gj = 0;  // (g0 * j) mod 255
+  for (int q = 0; q < SynShape<ID>::Q; ++q) sa[q] = 0;
 #pragma unroll 1
-    for (int j = 0; j < G::n1; ++j) {
-      const uint32_t c = cs[j];
-      const uint32_t width = c ? 8u : 0u;
-      uint32_t e = red255(tab(log4, c) + gj);  // log c_j + g0 j
-#pragma unroll
-      for (int i = 0; i < SG; ++i) {
-        if (i < gn) {
-          e = red255(e + (uint32_t)j);
-          acc[i] ^= tab(exp4, e, width);
-        }
-      }
-      gj = red255(gj + (uint32_t)g0);
-    }
-#pragma unroll
-    for (int i = 0; i < SG; ++i)
-      if (i < gn) S[g0 + i] = acc[i];
-    wave_sync();  // keeps the groups apart in the schedule
-  }
+  for (int j = 0; j < G::n1; ++j) add_rows(sa, (uint32_t)cs[j], syn_rows<ID>().r[j]);
   // reversed log-syndromes: my[m] = log S_{TD-m} (m < TD), zero marks after
 #pragma unroll
-  for (int m = 0; m < TD; ++m) my[m] = (uint16_t)logz(log4, S[TD - 1 - m]);
+  for (int m = 0; m < TD; ++m) my[m] = (uint16_t)logz(log4, byte_of(sa, TD - 1 - m));
 #pragma unroll
   for (int m = TD; m < 2 * TD; ++m) my[m] = (uint16_t)ZL;
 
@@ -444,7 +534,12 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 #pragma unroll
   for (int i = 0; i <= TD; ++i) ll[i] = logz(log4, lam[i]);
 
-  // S9 (part): Omega = S(x) Lambda(x) mod x^TD; my[2 TD + e] = log Omega_e
+  // S9 (part): Omega = S(x) Lambda(x) mod x^TD, each coefficient folded into
+  // Omega(X^-1) at the message positions as soon as it is known
+  const auto &ev = eval_rows<ID>();
+  uint32_t aw[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) aw[p] = 0;
 #pragma unroll 1
   for (int e = 0; e < TD; ++e) {
     const uint16_t *sp = my + (TD - e - 1);  // sp[i] = log S_{e+1-i}
@@ -452,26 +547,33 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 #pragma unroll
     for (int i = 0; i <= TD; ++i)
       if (i <= e) om ^= expz(exp4, ll[i] + sp[i]);
-    my[2 * TD + e] = (uint16_t)logz(log4, om);
+    add_rows(aw, om, ev.r[e]);
   }
-
-  // S8-S10: Chien + Forney at message position j = TD + t, then m_t (four
-  // bytes of m to a dword store)
-  const uint16_t *lom = my + 2 * TD;
-  uint32_t pack = 0;
+  // S8: the even and odd parts of Lambda(X^-1).  Lambda goes through the
+  // lane's LDS row (the syndromes are no longer needed) so that the loop over
+  // its coefficients is a loop, its rows read per step.
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i <= TD; ++i) my[i] = (uint16_t)lam[i];
+  wave_sync();
+  uint32_t ae[P], ao[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) ae[p] = ao[p] = 0;
 #pragma unroll 1
+  for (int i = 0; i < TD; i += 2) {
+    add_rows(ae, (uint32_t)my[i], ev.r[i]);
+    add_rows(ao, (uint32_t)my[i + 1], ev.r[i + 1]);
+  }
+  add_rows(ae, lam[TD], ev.r[TD]);
+
+  // S10: Forney at message position j = TD + t, then m_t (four bytes of m
+  // to a dword store)
+  uint32_t pack = 0;
+#pragma unroll
   for (int t = 0; t < G::k; ++t) {
     const uint32_t j = (uint32_t)(TD + t);
-    uint32_t ex = 0;  // (-i j) mod 255
-    uint32_t lamv = 0, oddv = 0, omv = 0;
-#pragma unroll
-    for (int i = 0; i <= TD; ++i) {
-      if (i > 0) ex = red255(ex + 255u - j);
-      const uint32_t tl = expz(exp4, ll[i] + ex);
-      lamv ^= tl;
-      if (i & 1) oddv ^= tl;
-      if (i < TD) omv ^= expz(exp4, lom[i] + ex);
-    }
+    const uint32_t oddv = byte_of(ao, t), omv = byte_of(aw, t);
+    const uint32_t lamv = byte_of(ae, t) ^ oddv;
     // e_j = Omega(X^-1) / Lambda'(X^-1) with Lambda'(X^-1) = X * odd(X^-1), X = alpha^j
     const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
     uint32_t e = tab(exp4, red255(x + 255u - j));
@@ -487,52 +589,41 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 // ---- S6-S10 with two lanes per item (tiles of at most 32 items) ---------------
 // Lanes l and l + 32 decode the same word.  Half h = l / 32 computes the
 // syndromes S_{hH+1} .. S_{hH+H} (H = delta) and holds the coefficients
-// 2i + h of Lambda and of B'; a discrepancy, an evaluator coefficient or a
-// value of Lambda / Omega is the XOR of the two halves' partial sums, and
-// the shift x * B' crosses between the halves, both through
-// v_permlane32_swap_b32.  The pair shares one LDS row `my`.
+// 2i + h of Lambda and of B'; a discrepancy or an evaluator coefficient is
+// the XOR of the two halves' partial sums, and the shift x * B' crosses
+// between the halves, both through v_permlane32_swap_b32.  The pair shares
+// one LDS row `my`.
 template <int ID, int OP>
 __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, uint16_t *my, uint32_t exp4,
-                                        uint32_t log4) {
+                                        const uint8_t *cs, uint16_t *my, GfTab exp4,
+                                        GfTab log4) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
   constexpr int H = TD / 2;
+  constexpr int P = EvalShape<ID>::P;
   const bool hi = lane_id() >= 32;
   const uint32_t h = hi ? 1u : 0u;
 
-  // S6: this half's H syndromes, in groups of SG
+  // S6: this half's H syndromes.  The upper half first multiplies c_j by
+  // alpha^(H j), so that S_{H+i} = sum_j (c_j alpha^(H j)) alpha^(i j) uses
+  // the rows of S_i.
   {
-    constexpr int SG = H <= 16 ? H : 10;
+    constexpr int QP = (H + 3) / 4;
     const uint32_t base = hi ? (uint32_t)H : 0u;
+    uint32_t sa[QP];
+#pragma unroll
+    for (int q = 0; q < QP; ++q) sa[q] = 0;
+    uint32_t gj = 0;  // (h H j) mod 255
+#pragma unroll 1
+    for (int j = 0; j < G::n1; ++j) {
+      const uint32_t c = cs[j];
+      const uint32_t cp = expz(exp4, logz(log4, c) + gj);
+      gj = red255(gj + base);
+      add_rows(sa, cp, syn_rows<ID>().r[j]);
+    }
     uint16_t *dst = my + (TD - 1) - (int)base;  // dst[-i] = my[TD - (base + i + 1)]
 #pragma unroll
-    for (int g0 = 0; g0 < H; g0 += SG) {
-      const int gn = H - g0 < SG ? H - g0 : SG;
-      const uint32_t step = base + (uint32_t)g0;
-      uint32_t acc[SG];
-#pragma unroll
-      for (int i = 0; i < SG; ++i) acc[i] = 0;
-      uint32_t gj = 0;  // (step * j) mod 255
-#pragma unroll 1
-      for (int j = 0; j < G::n1; ++j) {
-        const uint32_t c = cs[j];
-        const uint32_t width = c ? 8u : 0u;
-        uint32_t e = red255(tab(log4, c) + gj);
-#pragma unroll
-        for (int i = 0; i < SG; ++i) {
-          if (i < gn) {
-            e = red255(e + (uint32_t)j);
-            acc[i] ^= tab(exp4, e, width);
-          }
-        }
-        gj = red255(gj + step);
-      }
-#pragma unroll
-      for (int i = 0; i < SG; ++i)
-        if (i < gn) dst[-(g0 + i)] = (uint16_t)logz(log4, acc[i]);
-      wave_sync();
-    }
+    for (int i = 0; i < H; ++i) dst[-i] = (uint16_t)logz(log4, byte_of(sa, i));
 #pragma unroll
     for (int i = 0; i < H; ++i) my[TD + (int)base + i] = (uint16_t)ZL;
     wave_sync();
@@ -587,41 +678,55 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
 #pragma unroll
   for (int i = 0; i <= H; ++i) ll[i] = logz(log4, lam[i]);
 
-  // S9 (part): Omega_e = sum_{i <= e} Lambda_i S_{e+1-i}; both halves store
-  // the same value
-#pragma unroll 1
-  for (int e = 0; e < TD; ++e) {
-    const uint16_t *sp = my + (TD - e - 1) + (int)h;  // sp[2i] = log S_{e+1-2i-h}
-    uint32_t om = 0;
+  // S9 (part): Omega_e = sum_{i <= e} Lambda_i S_{e+1-i}, both halves
+  // getting the whole value; half h folds the coefficients 2i + h into
+  // W_h = sum_i Omega_{2i+h} X^(-2i) at the message positions
+  const auto &ev = eval_rows<ID>();
+  uint32_t aw[P];
 #pragma unroll
-    for (int i = 0; i <= H; ++i)
-      if (2 * i <= e) om ^= expz(exp4, ll[i] + sp[2 * i]);
-    const Halves ov = halves(om);
-    my[2 * TD + e] = (uint16_t)logz(log4, ov.lo ^ ov.hi);
-  }
-  wave_sync();
-
-  // S8-S10: each half evaluates its own coefficients (all odd ones are in
-  // the upper half, so its partial sum of Lambda is the odd part)
-  const uint16_t *lom = my + 2 * TD + (int)h;  // lom[2i] = log Omega_{2i+h}
-  uint32_t pack = 0;
+  for (int p = 0; p < P; ++p) aw[p] = 0;
 #pragma unroll 1
+  for (int e2 = 0; e2 < H; ++e2) {
+    uint32_t omv[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int e = 2 * e2 + d;
+      const uint16_t *sp = my + (TD - e - 1) + (int)h;  // sp[2i] = log S_{e+1-2i-h}
+      uint32_t om = 0;
+#pragma unroll
+      for (int i = 0; i <= H; ++i)
+        if (2 * i <= e) om ^= expz(exp4, ll[i] + sp[2 * i]);
+      const Halves ov = halves(om);
+      omv[d] = ov.lo ^ ov.hi;
+    }
+    add_rows(aw, hi ? omv[1] : omv[0], ev.r[2 * e2]);
+  }
+  // S8: P_h = sum_i Lambda_{2i+h} X^(-2i), so that Lambda(X^-1) = P_0 + X^-1 P_1
+  // and the odd part of Lambda at X^-1 is X^-1 P_1
+  // (Lambda goes through the pair's LDS row, so that this is a loop)
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i <= H; ++i) my[2 * i + (int)h] = (uint16_t)lam[i];
+  wave_sync();
+  uint32_t al[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) al[p] = 0;
+#pragma unroll 1
+  for (int i = 0; i <= H; ++i) add_rows(al, (uint32_t)my[2 * i + (int)h], ev.r[2 * i]);
+
+  // S10: with X = alpha^j, Lambda'(X^-1) = X * odd(X^-1) = P_1, so the error
+  // value is Omega(X^-1) / P_1 = (W_0 + X^-1 W_1) / P_1: half h contributes
+  // W_h X^(-h) / P_1.  j is a root position when P_1 != 0 and
+  // P_0 = X^-1 P_1.
+  uint32_t pack = 0;
+#pragma unroll
   for (int t = 0; t < G::k; ++t) {
     const uint32_t j = (uint32_t)(TD + t);
-    const uint32_t stp = 255u - 2u * j;         // -2j mod 255
-    uint32_t ex = hi ? 255u - j : 0u;            // -(2i + h) j mod 255
-    uint32_t lamp = 0, omp = 0;
-#pragma unroll
-    for (int i = 0; i <= H; ++i) {
-      if (i > 0) ex = red255(ex + stp);
-      lamp ^= expz(exp4, ll[i] + ex);
-      if (i < H) omp ^= expz(exp4, lom[2 * i] + ex);
-    }
-    const Halves lv = halves(lamp), wv = halves(omp);
-    const uint32_t lamv = lv.lo ^ lv.hi, oddv = lv.hi, omv = wv.lo ^ wv.hi;
-    const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
-    uint32_t e = tab(exp4, red255(x + 255u - j));
-    e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
+    const Halves lv = halves(logz(log4, byte_of(al, t)));  // log P_0, log P_1
+    const uint32_t lw = red255(logz(log4, byte_of(aw, t)) + (hi ? 255u - j : 0u));
+    const Halves tv = halves(expz(exp4, lw + 255u - (lv.hi & 0xFFu)));
+    const bool root = lv.hi < ZL && lv.lo == red255(lv.hi + 255u - j);
+    const uint32_t e = root ? (tv.lo ^ tv.hi) : 0u;
     pack |= ((cs[j] ^ e) & 0xFFu) << (8 * (t & 3));
     if ((t & 3) == 3) {
       if (active && !hi) ((uint32_t *)(sg.m + (size_t)item * G::k))[t >> 2] = pack;
@@ -632,7 +737,7 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
 
 template <int ID, int OP>
 __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
-                                        uint32_t exp4, uint32_t log4) {
+                                        GfTab exp4, GfTab log4) {
   using G = Geo<ID>;
   const int lane = lane_id();
   uint8_t *sym = (uint8_t *)lds + G::A_BYTES;
@@ -709,7 +814,7 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
 // a tile of nt <= 64 items; HQC-5 takes it 32 items at a time
 template <int ID, int OP>
 __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
-                                         uint32_t exp4, uint32_t log4) {
+                                         GfTab exp4, GfTab log4) {
   using G = Geo<ID>;
   if constexpr (G::COMPACT) {
     for (int s0 = 0; s0 < nt; s0 += G::TROWS)
@@ -721,10 +826,10 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
 }
 
 template <int OP, unsigned MASK>
-__global__ __launch_bounds__(64) void hqc_kernel(KArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hqc_kernel(KArgs a) {
   extern __shared__ uint32_t lds[];
-  const uint32_t exp4 = kGf.exp4[lane_id()];
-  const uint32_t log4 = kGf.log4[lane_id()];
+  const GfTab exp4 = gf_exp_tab();
+  const GfTab log4 = gf_log_tab();
   for (uint32_t unit = blockIdx.x; unit < a.total; unit += gridDim.x) {
     int s = 0;
     if (a.nseg > 1 && unit >= a.seg[1].first) s = 1;

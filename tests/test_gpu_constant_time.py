@@ -1,0 +1,99 @@
+"""Timing check of the decryption kernel against its input data, in the style
+of dudect (Reparaz, Balasch, Verbauwhede, "Dude, is my code constant time?",
+2017): per-launch device times of input classes, interleaved in random
+order.
+
+Classes (count items each):
+  zero:   one fixed key, u = 0, v = codewords of random messages (the decoder
+          sees no error at all: every syndrome is zero, Lambda = 1);
+  honest: one fixed key, honest ciphertexts (a few symbol errors per word);
+  random: fresh random keys and uniformly random (u, v) (every word is past
+          the decoding radius, so Berlekamp-Massey runs at full degree).
+
+Every loop bound, branch and memory address of the kernel, and every LDS
+bank pattern of its table reads, is independent of these values (the
+instruction and LDS bank-conflict counters of the classes are identical
+under rocprofv3).  Launch times still differ slightly with the data itself:
+the all-zero class runs about 1.4 % faster than random data, and honest
+ciphertexts about 0.2 % faster, an effect of the switching activity of the
+data on the chip's power and clock, not of the code path.  A t statistic
+would flag that effect at any size given enough launches, so the test
+bounds the relative difference of the means instead: a control-flow
+shortcut (an early exit on zero syndromes, a degree-dependent loop) would
+move the means by far more than these bounds."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12904_amd import synth
+from tests import datasets
+
+pytestmark = pytest.mark.gpu
+
+# bounds on |mean(class) / mean(random) - 1|
+HONEST_BOUND = 0.01
+ZERO_BOUND = 0.03
+
+
+def welch_t(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return (a.mean() - b.mean()) / np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+
+
+@pytest.mark.parametrize("pid", [1, 5])
+def test_decrypt_time_independent_of_data(pid):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc
+    print("case: constant time pid=%d" % pid, flush=True)
+    p = datasets.sizes(pid)
+    count = 16384
+    dev = "cuda"
+
+    def T(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(dev)
+
+    h, x, y = synth.keys(0xC7A + pid, pid, p, 1)
+    m = synth.encryptions(0xC7A + pid, pid, p, 64)[0]
+    cw = np.stack([oracle.code_encode(pid, mm) for mm in m])
+    classes = {
+        "zero": (torch.zeros((count, p["nwords"]), dtype=torch.int64, device=dev),
+                 T(cw[np.arange(count) % 64], np.int64), T(np.repeat(y, count, axis=0), np.int32)),
+    }
+    d = datasets.pke(pid, 512, 0xC7E + pid, shared_key=True)
+    idx = np.arange(count) % 512
+    classes["honest"] = (T(d["u"][idx], np.int64), T(d["v"][idx], np.int64), T(d["y"][idx], np.int32))
+    classes["random"] = (T(synth.words(0xC7C + pid, (count, p["nwords"])), np.int64),
+                         T(synth.words(0xC7D + pid, (count, p["vwords"])), np.int64),
+                         T(synth.keys(0xC7B + pid, pid, p, count)[2], np.int32))
+    names = list(classes)
+    out = torch.empty((count, p["k"]), dtype=torch.uint8, device=dev)
+    for _ in range(5):
+        for n in names:
+            hqc.decrypt_batch(pid, *classes[n], out=out)
+    torch.cuda.synchronize()
+    # the decoded messages of the honest class are right (the timing is of
+    # real decryptions)
+    hqc.decrypt_batch(pid, *classes["honest"], out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), d["m"][idx])
+
+    reps = 150
+    order = np.random.default_rng(pid).permutation(np.repeat(np.arange(len(names)), reps))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in order]
+    for (a, b), c in zip(ev, order):
+        a.record()
+        hqc.decrypt_batch(pid, *classes[names[c]], out=out)
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    # drop the slowest 5 % of each class (interrupts, clock steps), as dudect does
+    keep = int(0.95 * reps)
+    ts = {n: np.sort(t[order == i])[:keep] for i, n in enumerate(names)}
+    for n in names:
+        print("pid %d %-6s mean %.4f ms  sd %.4f  t vs random %.2f" % (
+            pid, n, ts[n].mean(), ts[n].std(), welch_t(ts[n], ts["random"])), flush=True)
+    rel = {n: ts[n].mean() / ts["random"].mean() - 1.0 for n in names}
+    assert abs(rel["honest"]) < HONEST_BOUND, rel
+    assert abs(rel["zero"]) < ZERO_BOUND, rel
