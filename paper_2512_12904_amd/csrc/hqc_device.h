@@ -40,10 +40,6 @@ template <int ID> struct Geo {
   static constexpr int U2 = 64 * R + DW + 2;         // doubled-u dwords (covers every window)
   static constexpr int RB = n1 * BSTR;               // received-word dwords
   static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
-  // Reed-Solomon scratch per lane (uint16 entries): reversed log-syndromes
-  // (2 TD entries, zero-padded)
-  static constexpr int RS_BYTES_LANE = odd_dword_stride(2 * 2 * TD);
-  static constexpr int RS_STR = RS_BYTES_LANE / 2;   // in uint16 entries
   static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
   // HQC-5 runs a tile as sub-tiles of at most 32 items (two lanes per
   // Reed-Solomon word) and builds the received word over the doubled u once
@@ -59,7 +55,7 @@ template <int ID> struct Geo {
   // of 32 pairs (1.5 full passes) instead of 2 passes of 64 lanes
   static constexpr bool PAIR_RM = ID == 5;
   static constexpr int A_BYTES =
-      (cmax(4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB), TROWS * RS_BYTES_LANE) + 15) / 16 * 16;
+      (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
   static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
   static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");

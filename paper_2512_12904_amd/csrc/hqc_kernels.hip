@@ -459,14 +459,123 @@ __device__ __forceinline__ uint32_t byte_of(const uint32_t *a, int t) {
   return __builtin_amdgcn_ubfe(a[t >> 2], 8 * (t & 3), 8);
 }
 
+// ---- Bit-sliced GF(2^8) vectors ------------------------------------------------
+// A vector of field elements is held as 8 bit planes: bit i of plane j is
+// bit j of element i, NC dwords per plane (element i in dword i / 32).
+// Multiplying the whole vector by a scalar c is sum_k c_k (alpha^k T), and
+// alpha x on planes is a renaming plus three XORs (alpha^8 = alpha^4 +
+// alpha^3 + alpha^2 + 1): 64 v_bitop3 and 21 XORs per 32 elements, with the
+// scalar's bits as all-ones / all-zero masks and no table read.
+
+// D ^= c T, cm[k] = the mask of bit k of c
+template <int NC>
+__device__ __forceinline__ void mul_acc(uint32_t (&D)[8][NC], const uint32_t (&T)[8][NC],
+                                        const uint32_t (&cm)[8]) {
+  uint32_t cur[8][NC];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) cur[j][q] = T[j][q];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    // truth table 0x6C: S1 ^ (S0 & S2)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) D[j][q] = __builtin_amdgcn_bitop3_b32(cur[j][q], D[j][q], cm[k], 0x6C);
+    if (k < 7) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const uint32_t c7 = cur[7][q];
+        cur[7][q] = cur[6][q];
+        cur[6][q] = cur[5][q];
+        cur[5][q] = cur[4][q];
+        cur[4][q] = cur[3][q] ^ c7;
+        cur[3][q] = cur[2][q] ^ c7;
+        cur[2][q] = cur[1][q] ^ c7;
+        cur[1][q] = cur[0][q];
+        cur[0][q] = c7;
+      }
+    }
+  }
+}
+
+// o = a << 1 across NC dwords
+template <int NC>
+__device__ __forceinline__ void shl1(const uint32_t (&a)[NC], uint32_t (&o)[NC]) {
+  o[0] = a[0] << 1;
+#pragma unroll
+  for (int q = 1; q < NC; ++q) o[q] = __builtin_amdgcn_alignbit(a[q], a[q - 1], 31);
+}
+
+// clear the bits of elements >= n
+template <int NC>
+__device__ __forceinline__ void keep_elems(uint32_t (&P)[8][NC], int n) {
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const uint32_t m = n >= 32 * (q + 1) ? ~0u : (n > 32 * q ? (1u << (n - 32 * q)) - 1u : 0u);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) P[j][q] &= m;
+  }
+}
+
+// masks of the 8 bits of element i (dword col of the planes, col public)
+template <int NC>
+__device__ __forceinline__ void elem_masks(const uint32_t (&P)[8][NC], bool upper, uint32_t off,
+                                           uint32_t (&m)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    m[j] = (uint32_t)__builtin_amdgcn_sbfe((int)((NC > 1 && upper) ? P[j][NC - 1] : P[j][0]), off, 1);
+}
+
+// ---- S7: Berlekamp-Massey on bit-sliced vectors --------------------------------
+// Massey's recursion (Lambda <- Lambda + (Delta / b) x^s B, B <- Lambda and
+// b <- Delta when 2L <= r - 1) in the reformulated form of Sarwate and
+// Shanbhag (riBM): the discrepancies are not inner products but the low
+// part of a vector D that is updated like Lambda.  With D holding
+// S_1 .. S_2delta in region A and Lambda in region C (coefficient q at
+// element q), step r is
+//     Delta = D_A[r],  c = Delta / gamma,
+//     U = swap ? D : T,  D <- D + c T,  T <- x U,
+//     gamma <- swap ? Delta : gamma,
+// swap = (Delta != 0 and 2L <= r), on both regions alike (T starts as x D).
+// Region C then holds Lambda times a nonzero constant (the same Lambda
+// sequence as Massey's form; roots and Omega / Lambda' are unchanged).
+// Elements of region A below r and of region C above 2 delta are never
+// read; they only move upwards, so they never reach the live elements.
+template <int NC>
+__device__ __forceinline__ void bm_step(uint32_t (&D)[8][NC], uint32_t (&T)[8][NC],
+                                        const uint32_t (&cm)[8], bool sw) {
+  uint32_t U[8][NC];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) U[j][q] = sw ? D[j][q] : T[j][q];
+  mul_acc(D, T, cm);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) shl1(U[j], T[j]);
+}
+
+// Delta = element r of region A (r uniform), as a byte
+template <int NC>
+__device__ __forceinline__ uint32_t elem_byte(const uint32_t (&P)[8][NC], int r) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t w = (NC > 1 && r >= 32) ? P[j][NC - 1] : P[j][0];
+    d |= __builtin_amdgcn_ubfe(w, (uint32_t)r & 31u, 1) << j;
+  }
+  return d;
+}
+
 // ---- S6-S10: Reed-Solomon decode of one item per lane ------------------------
 template <int ID, int OP>
 __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, uint16_t *my, GfTab exp4,
-                                        GfTab log4) {
+                                        const uint8_t *cs, GfTab exp4, GfTab log4) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
   constexpr int P = EvalShape<ID>::P;
+  constexpr int NCA = (TD + 31) / 32, NCC = (TD + 1 + 31) / 32;
 
   // S6: S_i = sum_j c_j alpha^(i j), i = 1 .. TD; byte i - 1 of sa (four to
   // a dword) is S_i
@@ -475,96 +584,107 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
   for (int q = 0; q < SynShape<ID>::Q; ++q) sa[q] = 0;
 #pragma unroll 1
   for (int j = 0; j < G::n1; ++j) add_rows(sa, (uint32_t)cs[j], syn_rows<ID>().r[j]);
-  // reversed log-syndromes: my[m] = log S_{TD-m} (m < TD), zero marks after
+  // S(x) = sum_i S_i x^(i-1) as planes
+  uint32_t SP[8][NCA];
 #pragma unroll
-  for (int m = 0; m < TD; ++m) my[m] = (uint16_t)logz(log4, byte_of(sa, TD - 1 - m));
+  for (int j = 0; j < 8; ++j) {
 #pragma unroll
-  for (int m = TD; m < 2 * TD; ++m) my[m] = (uint16_t)ZL;
-
-  // S7: Berlekamp-Massey, B' = x^s B / b kept as logs (lb).  After step r,
-  // deg Lambda <= r and deg B' <= r + 1, so step r touches i <= r + 1 only.
-  // For the smaller sets the logs of Lambda found for the discrepancy are
-  // kept for the update; for HQC-5 they are recomputed to save registers.
-  constexpr bool KEEP_LL = TD <= 32;
-  uint32_t lam[TD + 1], lb[TD + 1], llk[KEEP_LL ? TD + 1 : 1];
+    for (int q = 0; q < NCA; ++q) SP[j][q] = 0;
 #pragma unroll
-  for (int i = 0; i <= TD; ++i) {
-    lam[i] = i == 0 ? 1u : 0u;
-    lb[i] = i == 1 ? 0u : ZL;
+    for (int m = 0; m < TD; ++m)
+      SP[j][m >> 5] |= __builtin_amdgcn_ubfe(sa[m >> 2], 8 * (m & 3) + j, 1) << (m & 31);
   }
-  uint32_t L = 0;
+
+  // S7: region A = S_1 .. S_TD, region C = Lambda
+  uint32_t DA[8][NCA], TA[8][NCA], DC[8][NCC], TC[8][NCC];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+#pragma unroll
+    for (int q = 0; q < NCA; ++q) DA[j][q] = SP[j][q];
+    shl1(SP[j], TA[j]);
+#pragma unroll
+    for (int q = 0; q < NCC; ++q) {
+      DC[j][q] = (j == 0 && q == 0) ? 1u : 0u;
+      TC[j][q] = (j == 0 && q == 0) ? 2u : 0u;
+    }
+  }
+  {
+    uint32_t lg = 0;  // log gamma
+    int kk = 0;       // r - 2L
 #pragma unroll 1
-  for (int r = 1; r <= TD; ++r) {
-    const uint16_t *sp = my + (TD - r);  // sp[i] = log S_{r-i} (zero mark when i >= r)
-    uint32_t delta = 0;
+    for (int r = 0; r < TD; ++r) {
+      const uint32_t d0 = elem_byte(DA, r);
+      const uint32_t ld = logz(log4, d0);
+      const uint32_t c = expz(exp4, ld + 255u - lg);
+      const bool sw = d0 != 0 && kk >= 0;
+      uint32_t cm[8];
 #pragma unroll
-    for (int i = 0; i <= TD; ++i) {
-      if (i < r) {
-        const uint32_t li = logz(log4, lam[i]);
-        if constexpr (KEEP_LL) llk[i] = li;
-        delta ^= expz(exp4, li + sp[i]);
-      }
+      for (int k = 0; k < 8; ++k) cm[k] = (uint32_t)__builtin_amdgcn_sbfe((int)c, k, 1);
+      bm_step(DA, TA, cm, sw);
+      bm_step(DC, TC, cm, sw);
+      lg = sw ? (ld & 0xFFu) : lg;
+      kk = sw ? -kk - 1 : kk + 1;
     }
-    const uint32_t lD = logz(log4, delta);
-    const bool swap = delta != 0 && 2 * L <= (uint32_t)(r - 1);
-    const uint32_t nlD = 255u - (lD & 0xFFu);
-#pragma unroll
-    for (int i = TD; i >= 0; --i) {
-      if (i <= r + 1) {
-        if (i <= r) lam[i] ^= expz(exp4, lD + lb[i]);
-        if (i >= 1) {
-          // B'_new[i] = x * (swap ? Lambda_old / Delta : B')[i - 1]; lam[i-1]
-          // is still the old coefficient (the loop runs downwards)
-          uint32_t q = ZL;
-          if (i - 1 < r) {
-            const uint32_t li = KEEP_LL ? llk[KEEP_LL ? i - 1 : 0] : logz(log4, lam[i - 1]);
-            q = red255(li + nlD);
-          }
-          lb[i] = swap ? q : lb[i - 1];
-        } else {
-          lb[0] = ZL;
-        }
-      }
-    }
-    L = swap ? (uint32_t)r - L : L;
   }
+  keep_elems(DC, TD + 1);
 
-  // final logs of Lambda
-  uint32_t ll[TD + 1];
+  // S9 (part): Omega = S(x) Lambda(x) mod x^TD, by Horner over Lambda's
+  // coefficients: W <- x W + Lambda_i S
+  uint32_t W[8][NCA];
 #pragma unroll
-  for (int i = 0; i <= TD; ++i) ll[i] = logz(log4, lam[i]);
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < NCA; ++q) W[j][q] = 0;
+#pragma unroll 1
+  for (int i = TD; i >= 0; --i) {
+    uint32_t lm[8];
+    elem_masks(DC, i >= 32, (uint32_t)i & 31u, lm);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t t[NCA];
+      shl1(W[j], t);
+#pragma unroll
+      for (int q = 0; q < NCA; ++q) W[j][q] = t[q];
+    }
+    mul_acc(W, SP, lm);
+  }
+  keep_elems(W, TD);
 
-  // S9 (part): Omega = S(x) Lambda(x) mod x^TD, each coefficient folded into
-  // Omega(X^-1) at the message positions as soon as it is known
+  // S8 + S9: Lambda (even and odd parts) and Omega at X^-1 for the message
+  // positions X = alpha^(TD + t): the bits of each coefficient select rows
   const auto &ev = eval_rows<ID>();
-  uint32_t aw[P];
+  uint32_t ae[P], ao[P], aw[P];
 #pragma unroll
-  for (int p = 0; p < P; ++p) aw[p] = 0;
+  for (int p = 0; p < P; ++p) ae[p] = ao[p] = aw[p] = 0;
 #pragma unroll 1
-  for (int e = 0; e < TD; ++e) {
-    const uint16_t *sp = my + (TD - e - 1);  // sp[i] = log S_{e+1-i}
-    uint32_t om = 0;
+  for (int i = 0; i <= TD; i += 2) {
+    uint32_t lm[8], wm[8];
+    elem_masks(DC, i >= 32, (uint32_t)i & 31u, lm);
+    elem_masks(W, i >= 32, (uint32_t)i & 31u, wm);
+    if (i == TD) {  // Omega has TD coefficients
 #pragma unroll
-    for (int i = 0; i <= TD; ++i)
-      if (i <= e) om ^= expz(exp4, ll[i] + sp[i]);
-    add_rows(aw, om, ev.r[e]);
+      for (int b = 0; b < 8; ++b) wm[b] = 0;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        ae[p] = __builtin_amdgcn_bitop3_b32(ev.r[i][b][p], ae[p], lm[b], 0x6C);
+        aw[p] = __builtin_amdgcn_bitop3_b32(ev.r[i][b][p], aw[p], wm[b], 0x6C);
+      }
+    if (i < TD) {
+      const int i1 = i + 1;
+      elem_masks(DC, i1 >= 32, (uint32_t)i1 & 31u, lm);
+      elem_masks(W, i1 >= 32, (uint32_t)i1 & 31u, wm);
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          ao[p] = __builtin_amdgcn_bitop3_b32(ev.r[i1][b][p], ao[p], lm[b], 0x6C);
+          aw[p] = __builtin_amdgcn_bitop3_b32(ev.r[i1][b][p], aw[p], wm[b], 0x6C);
+        }
+    }
   }
-  // S8: the even and odd parts of Lambda(X^-1).  Lambda goes through the
-  // lane's LDS row (the syndromes are no longer needed) so that the loop over
-  // its coefficients is a loop, its rows read per step.
-  wave_sync();
-#pragma unroll
-  for (int i = 0; i <= TD; ++i) my[i] = (uint16_t)lam[i];
-  wave_sync();
-  uint32_t ae[P], ao[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) ae[p] = ao[p] = 0;
-#pragma unroll 1
-  for (int i = 0; i < TD; i += 2) {
-    add_rows(ae, (uint32_t)my[i], ev.r[i]);
-    add_rows(ao, (uint32_t)my[i + 1], ev.r[i + 1]);
-  }
-  add_rows(ae, lam[TD], ev.r[TD]);
 
   // S10: Forney at message position j = TD + t, then m_t (four bytes of m
   // to a dword store)
@@ -588,31 +708,31 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 
 // ---- S6-S10 with two lanes per item (tiles of at most 32 items) ---------------
 // Lanes l and l + 32 decode the same word.  Half h = l / 32 computes the
-// syndromes S_{hH+1} .. S_{hH+H} (H = delta) and holds the coefficients
-// 2i + h of Lambda and of B'; a discrepancy or an evaluator coefficient is
-// the XOR of the two halves' partial sums, and the shift x * B' crosses
-// between the halves, both through v_permlane32_swap_b32.  The pair shares
-// one LDS row `my`.
+// syndromes S_{hH+1} .. S_{hH+H} (H = delta); in Berlekamp-Massey the lower
+// half holds region A and the upper half region C, the discrepancy crossing
+// through v_permlane32_swap_b32; half h then takes Lambda's and Omega's
+// coefficients 2i + h for the evaluations.
 template <int ID, int OP>
 __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, uint16_t *my, GfTab exp4,
-                                        GfTab log4) {
+                                        const uint8_t *cs, GfTab exp4, GfTab log4) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
   constexpr int H = TD / 2;
   constexpr int P = EvalShape<ID>::P;
+  constexpr int NC = (TD + 1 + 31) / 32;
+  static_assert(H < 32 && TD + 1 <= 64, "pair layout");
   const bool hi = lane_id() >= 32;
   const uint32_t h = hi ? 1u : 0u;
 
   // S6: this half's H syndromes.  The upper half first multiplies c_j by
   // alpha^(H j), so that S_{H+i} = sum_j (c_j alpha^(H j)) alpha^(i j) uses
   // the rows of S_i.
-  {
-    constexpr int QP = (H + 3) / 4;
-    const uint32_t base = hi ? (uint32_t)H : 0u;
-    uint32_t sa[QP];
+  constexpr int QP = (H + 3) / 4;
+  uint32_t sa[QP];
 #pragma unroll
-    for (int q = 0; q < QP; ++q) sa[q] = 0;
+  for (int q = 0; q < QP; ++q) sa[q] = 0;
+  {
+    const uint32_t base = hi ? (uint32_t)H : 0u;
     uint32_t gj = 0;  // (h H j) mod 255
 #pragma unroll 1
     for (int j = 0; j < G::n1; ++j) {
@@ -621,98 +741,114 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
       gj = red255(gj + base);
       add_rows(sa, cp, syn_rows<ID>().r[j]);
     }
-    uint16_t *dst = my + (TD - 1) - (int)base;  // dst[-i] = my[TD - (base + i + 1)]
+  }
+  // S(x) = sum_i S_i x^(i-1) as planes, in both halves
+  uint32_t SP[8][NC];
 #pragma unroll
-    for (int i = 0; i < H; ++i) dst[-i] = (uint16_t)logz(log4, byte_of(sa, i));
+  for (int j = 0; j < 8; ++j) {
+    uint32_t pl = 0;  // this half's syndromes, bit i <-> S_{hH+i+1}
 #pragma unroll
-    for (int i = 0; i < H; ++i) my[TD + (int)base + i] = (uint16_t)ZL;
-    wave_sync();
+    for (int i = 0; i < H; ++i) pl |= __builtin_amdgcn_ubfe(sa[i >> 2], 8 * (i & 3) + j, 1) << i;
+    const Halves pv = halves(pl);
+    SP[j][0] = pv.lo | (pv.hi << H);
+    if constexpr (NC > 1) SP[j][1] = pv.hi >> (32 - H);
   }
 
-  // S7: Berlekamp-Massey on interleaved halves; register i holds coefficient
-  // 2i + h (coefficient TD + 1 of the upper half stays zero)
-  uint32_t lam[H + 1], lb[H + 1], llk[H + 1];
+  // S7: lower half region A = S_1 .. S_TD, upper half region C = Lambda
+  uint32_t D[8][NC], T[8][NC];
 #pragma unroll
-  for (int i = 0; i <= H; ++i) {
-    lam[i] = (i == 0 && !hi) ? 1u : 0u;
-    lb[i] = (i == 0 && hi) ? 0u : ZL;
-    llk[i] = ZL;
+  for (int j = 0; j < 8; ++j) {
+    uint32_t ta[NC];
+    shl1(SP[j], ta);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      D[j][q] = hi ? ((j == 0 && q == 0) ? 1u : 0u) : SP[j][q];
+      T[j][q] = hi ? ((j == 0 && q == 0) ? 2u : 0u) : ta[q];
+    }
   }
-  uint32_t L = 0;
+  {
+    uint32_t lg = 0;  // log gamma
+    int kk = 0;       // r - 2L
 #pragma unroll 1
-  for (int r = 1; r <= TD; ++r) {
-    const uint16_t *sp = my + (TD - r) + (int)h;  // sp[2i] = log S_{r - 2i - h}
-    uint32_t delta = 0;
+    for (int r = 0; r < TD; ++r) {
+      const uint32_t d0 = halves(elem_byte(D, r)).lo;  // the lower half's element r
+      const uint32_t ld = logz(log4, d0);
+      const uint32_t c = expz(exp4, ld + 255u - lg);
+      const bool sw = d0 != 0 && kk >= 0;
+      uint32_t cm[8];
 #pragma unroll
-    for (int i = 0; i <= H; ++i) {
-      if (2 * i < r) {
-        const uint32_t li = logz(log4, lam[i]);
-        llk[i] = li;
-        delta ^= expz(exp4, li + sp[2 * i]);
-      }
+      for (int k = 0; k < 8; ++k) cm[k] = (uint32_t)__builtin_amdgcn_sbfe((int)c, k, 1);
+      bm_step(D, T, cm, sw);
+      lg = sw ? (ld & 0xFFu) : lg;
+      kk = sw ? -kk - 1 : kk + 1;
     }
-    {
-      const Halves dv = halves(delta);
-      delta = dv.lo ^ dv.hi;
-    }
-    const uint32_t lD = logz(log4, delta);
-    const bool swap = delta != 0 && 2 * L <= (uint32_t)(r - 1);
-    const uint32_t nlD = 255u - (lD & 0xFFu);
-    uint32_t prev = ZL;  // B'_new[0]
-#pragma unroll
-    for (int i = 0; i <= H; ++i) {
-      if (2 * i <= r + 1) {
-        // what coefficient t = 2i + h passes on to B'_new[t + 1]
-        const uint32_t t = 2u * (uint32_t)i + h;
-        const uint32_t q = t < (uint32_t)r ? red255(llk[i] + nlD) : ZL;
-        const uint32_t src = swap ? q : lb[i];
-        lam[i] ^= expz(exp4, lD + lb[i]);
-        const Halves sv = halves(src);
-        lb[i] = hi ? sv.lo : prev;
-        prev = sv.hi;
-      }
-    }
-    L = swap ? (uint32_t)r - L : L;
   }
-  uint32_t ll[H + 1];
+  // Lambda (the upper half's region C) in both halves
+  uint32_t C[8][NC];
 #pragma unroll
-  for (int i = 0; i <= H; ++i) ll[i] = logz(log4, lam[i]);
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) C[j][q] = halves(D[j][q]).hi;
+  keep_elems(C, TD + 1);
 
-  // S9 (part): Omega_e = sum_{i <= e} Lambda_i S_{e+1-i}, both halves
-  // getting the whole value; half h folds the coefficients 2i + h into
-  // W_h = sum_i Omega_{2i+h} X^(-2i) at the message positions
+  // S9 (part): Omega = S(x) Lambda(x) mod x^TD by Horner, W <- x W + Lambda_i S:
+  // the lower half over i = H .. 0, the upper half over i = TD + 1 .. H + 1
+  // (Lambda_{TD+1} = 0), whose sum is then multiplied by x^(H+1)
+  uint32_t W[8][NC];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) W[j][q] = 0;
+#pragma unroll 1
+  for (int s = H; s >= 0; --s) {
+    const uint32_t i = (uint32_t)s + (hi ? (uint32_t)(H + 1) : 0u);
+    uint32_t lm[8];
+    elem_masks(C, i >= 32u, i & 31u, lm);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t t[NC];
+      shl1(W[j], t);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) W[j][q] = t[q];
+    }
+    mul_acc(W, SP, lm);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    uint32_t up[NC];  // W x^(H+1)
+    up[0] = W[j][0] << (H + 1);
+#pragma unroll
+    for (int q = 1; q < NC; ++q) up[q] = __builtin_amdgcn_alignbit(W[j][q], W[j][q - 1], 31 - H);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const Halves wv = halves(hi ? up[q] : W[j][q]);
+      W[j][q] = wv.lo ^ wv.hi;
+    }
+  }
+  keep_elems(W, TD);
+
+  // S8 + S9: P_h = sum_i Lambda_{2i+h} X^(-2i) and W_h = sum_i Omega_{2i+h}
+  // X^(-2i) at the message positions, so that Lambda(X^-1) = P_0 + X^-1 P_1,
+  // the odd part of Lambda at X^-1 is X^-1 P_1 and Omega(X^-1) = W_0 + X^-1 W_1
   const auto &ev = eval_rows<ID>();
-  uint32_t aw[P];
+  uint32_t al[P], aw[P];
 #pragma unroll
-  for (int p = 0; p < P; ++p) aw[p] = 0;
+  for (int p = 0; p < P; ++p) al[p] = aw[p] = 0;
 #pragma unroll 1
-  for (int e2 = 0; e2 < H; ++e2) {
-    uint32_t omv[2];
+  for (int i = 0; i <= H; ++i) {
+    const bool upper = 2 * i >= 32;
+    const uint32_t off = ((uint32_t)(2 * i) & 31u) + h;
+    uint32_t lm[8], wm[8];
+    elem_masks(C, upper, off, lm);
+    elem_masks(W, upper, off, wm);
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int e = 2 * e2 + d;
-      const uint16_t *sp = my + (TD - e - 1) + (int)h;  // sp[2i] = log S_{e+1-2i-h}
-      uint32_t om = 0;
+    for (int b = 0; b < 8; ++b)
 #pragma unroll
-      for (int i = 0; i <= H; ++i)
-        if (2 * i <= e) om ^= expz(exp4, ll[i] + sp[2 * i]);
-      const Halves ov = halves(om);
-      omv[d] = ov.lo ^ ov.hi;
-    }
-    add_rows(aw, hi ? omv[1] : omv[0], ev.r[2 * e2]);
+      for (int p = 0; p < P; ++p) {
+        al[p] = __builtin_amdgcn_bitop3_b32(ev.r[2 * i][b][p], al[p], lm[b], 0x6C);
+        aw[p] = __builtin_amdgcn_bitop3_b32(ev.r[2 * i][b][p], aw[p], wm[b], 0x6C);
+      }
   }
-  // S8: P_h = sum_i Lambda_{2i+h} X^(-2i), so that Lambda(X^-1) = P_0 + X^-1 P_1
-  // and the odd part of Lambda at X^-1 is X^-1 P_1
-  // (Lambda goes through the pair's LDS row, so that this is a loop)
-  wave_sync();
-#pragma unroll
-  for (int i = 0; i <= H; ++i) my[2 * i + (int)h] = (uint16_t)lam[i];
-  wave_sync();
-  uint32_t al[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) al[p] = 0;
-#pragma unroll 1
-  for (int i = 0; i <= H; ++i) add_rows(al, (uint32_t)my[2 * i + (int)h], ev.r[2 * i]);
 
   // S10: with X = alpha^j, Lambda'(X^-1) = X * odd(X^-1) = P_1, so the error
   // value is Omega(X^-1) / P_1 = (W_0 + X^-1 W_1) / P_1: half h contributes
@@ -793,14 +929,13 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   if constexpr (OP == OP_KEYED) {
     bad_key = sg.key_ids[item] >= sg.ks_cap;
   }
-  uint16_t *my = (uint16_t *)lds + s * G::RS_STR;
   if constexpr (G::COMPACT) {
-    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
   } else {
     if (pair)
-      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
     else
-      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, my, exp4, log4);
+      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
   }
   if constexpr (OP == OP_KEYED) {
     if (active && bad_key && s == lane) {
