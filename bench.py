@@ -353,6 +353,9 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=2.0)
     ap.add_argument("--tile", type=int, default=0, help="items per workgroup (0 = library)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups (0 = library)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's built-in launch configuration instead of running "
+                         "the autotuner for each set and batch size first")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decryption batch has no cross-GPU step; "
@@ -381,7 +384,11 @@ def main():
                                          for pid in sets}}), flush=True)
         return
     results = {}
+    tuned = {}
     for pid in sets:
+        if not args.no_autotune and GRID == 0 and TILE == 0:
+            # the library's autotuner picks (tile, grid) for this set and batch size
+            tuned[pid] = hqc.autotune_decrypt(pid, args.count, reps=5)
         u, v, y, m, gen = make_inputs(pid, args.count, 0xBE00 + pid, dev)
         out = torch.empty((args.count, SETS[pid]["k"]), dtype=torch.uint8, device=dev)
         steps = args.steps if pid == 1 else max(5, args.steps // 2)
@@ -407,6 +414,12 @@ def main():
             u = v = y = m = out = None
             r.update(kem_bench(hqc, pid, args.count, 0xC0DE + pid, dev))
         r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
+        if pid in tuned:
+            t = tuned[pid]
+            r["autotune"] = {"tile": t["tile"], "grid": t["grid"], "ms": round(t["ms"], 4),
+                             "default_tile": t["heuristic_tile"], "default_grid": t["heuristic_grid"],
+                             "default_ms": round(t["heuristic_ms"], 4),
+                             "candidates": t["candidates"], "identical": bool(t["identical"])}
         results[pid] = r
         del u, v, y, m, out
         torch.cuda.empty_cache()
@@ -432,7 +445,10 @@ def main():
         "data": "synthetic: seeded keys and randomness, ciphertexts from the GPU encryption",
         "config": {"workload": "HQC-%d PKE decrypt, batch %d in one persistent hipGraph launch"
                                % (pid0, args.count), "param_set": "HQC-%d" % pid0,
-                   "batch": args.count, "launch": "hipGraph, persistent grid"},
+                   "batch": args.count,
+                   "launch": "hipGraph, persistent grid, %s" % (
+                       "tile %d x grid %d from the autotuner" % (tuned[pid0]["tile"], tuned[pid0]["grid"])
+                       if pid0 in tuned else "tile %d / grid %d (0 = library default)" % (TILE, GRID))},
         "p50_launch_ms": main_r["ms_p50"],
         "p99_launch_ms": main_r["ms_p99"],
         "per_set": {"HQC-%d" % k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)

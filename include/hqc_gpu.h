@@ -249,6 +249,51 @@ int hqc_default_grid(int param_id);
 /* Releases cached graphs.  Keystores stay valid. */
 void hqc_shutdown(void);
 
+/* ---- Launch-configuration autotuner ------------------------------------
+ * The decryption kernels take two launch parameters that never change the
+ * results: the persistent grid (workgroups) and the tile (ciphertexts per
+ * workgroup tile, which also picks the Reed-Solomon mapping: two lanes per
+ * word for tiles of at most 32, one lane per word above).  The library
+ * keeps a table, per device, parameter set and batch-size bucket (the
+ * power of two at or above count), of the configuration to use when a
+ * single-set call leaves params->grid and params->tile at 0; without an
+ * entry it uses the occupancy grid and tile = ceil(count / grid), at most 64.
+ * Because the kernels' time does not depend on the data (constant time),
+ * configurations can be timed on random inputs. */
+typedef struct hqc_tune_report {
+  int32_t param_id;
+  int32_t tile, grid;            /* chosen configuration (now in the table) */
+  float ms;                      /* its median launch time */
+  int32_t heuristic_tile, heuristic_grid;
+  float heuristic_ms;            /* median time of the built-in default */
+  int32_t candidates;            /* configurations timed */
+  int32_t identical;             /* 1: every configuration gave byte-identical messages */
+  uint64_t count;
+} hqc_tune_report_t;
+
+/* Times candidate (tile, grid) pairs of the decryption kernel for param_id
+ * (1, 3 or 5) on count random ciphertexts (count in 1 .. 2^20): one untimed
+ * launch each, whose messages must all be byte-identical, then reps rounds
+ * that time every candidate once, on `stream` (NULL: null stream).  The
+ * candidate with the lowest median is stored in the table if it beats the
+ * built-in default by more than 1 %, else the default is (nothing is
+ * stored if any candidate's messages differed: out->identical = 0); *out
+ * gets the choice and both medians.  Allocates and frees its own device buffers
+ * (u, v, y, m: count * (8 u_words + 8 v_words + 4 w + k) bytes); blocks
+ * until done.  HQC_EINVAL: bad id, count 0, reps < 1 or out NULL;
+ * HQC_ERANGE: count > 2^20; HQC_ENOMEM / HQC_EHIP: allocation or HIP
+ * failure (the table is then unchanged). */
+int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *stream,
+                         hqc_tune_report_t *out);
+/* Sets the table entry of count's bucket on the current device (tile 1..64,
+ * grid >= 1); tile = grid = 0 removes it.  HQC_EINVAL otherwise. */
+int hqc_tune_set(int param_id, size_t count, int tile, int grid);
+/* The entry used for a call of count items: *tile and *grid, or 0 and 0
+ * when there is none.  HQC_EINVAL for a bad id or NULL pointers. */
+int hqc_tune_get(int param_id, size_t count, int *tile, int *grid);
+/* Empties the table (all devices). */
+void hqc_tune_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 GPU_SO = os.path.join(HERE, "libhqc_gpu.so")
 GPU_SOURCES = [os.path.join(CSRC, "hqc_kernels.hip"), os.path.join(CSRC, "hqc_encrypt.hip"),
                os.path.join(CSRC, "hqc_kem.hip"), os.path.join(CSRC, "hqc_ring.hip"),
+               os.path.join(CSRC, "hqc_tune.hip"),
                os.path.join(CSRC, "hqc_capi.cpp")]
 GPU_HEADERS = [os.path.join(CSRC, "hqc_internal.h"), os.path.join(CSRC, "hqc_internal_enc.h"),
                os.path.join(CSRC, "hqc_device.h"),

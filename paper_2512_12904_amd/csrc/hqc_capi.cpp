@@ -139,6 +139,41 @@ int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream
   return HQC_OK;
 }
 
+// Tuned launch configurations: (device, parameter set, batch-size bucket)
+// -> (tile, grid), filled by hqc_tune_set / hqc_autotune_decrypt.  The
+// bucket of a count is the exponent of the power of two at or above it.
+struct Tuned {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> table;
+};
+Tuned g_tuned;
+
+int count_bucket(uint64_t count) {
+  int b = 0;
+  while (b < 63 && (1ull << b) < count) ++b;
+  return b;
+}
+
+// current device, or -1 where there is none (the table still works)
+int device_or_none() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  return dev;
+}
+
+bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid) {
+  const auto key = std::make_tuple(device_or_none(), pid, count_bucket(count));
+  std::lock_guard<std::mutex> lk(g_tuned.mu);
+  auto it = g_tuned.table.find(key);
+  if (it == g_tuned.table.end()) return false;
+  *tile = it->second.first;
+  *grid = it->second.second;
+  return true;
+}
+
 // Splits the segments into tiles of `tile` items; returns the tile count.
 uint32_t assign_tiles(hqc::KArgs &a, uint32_t tile) {
   uint32_t t = 0;
@@ -162,8 +197,15 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
     int rc = default_grid(op, mask, &full);
     if (rc) return rc;
   }
-  if (grid <= 0) grid = full;
   uint32_t tile = (uint32_t)p->tile;
+  if (grid <= 0 && tile == 0 && (mask == 1u || mask == 2u || mask == 4u)) {
+    int tt = 0, tg = 0;
+    if (tuned_lookup(mask == 1u ? 1 : mask == 2u ? 3 : 5, items, &tt, &tg)) {
+      tile = (uint32_t)tt;
+      grid = tg;
+    }
+  }
+  if (grid <= 0) grid = full;
   if (tile == 0) {
     // enough tiles to give every resident workgroup one, at most 64 items each
     uint64_t per = (items + (uint64_t)grid - 1) / (uint64_t)grid;
@@ -763,6 +805,31 @@ int hqc_default_grid(int param_id) {
 void hqc_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_graphs.mu);
   clear_graphs_locked();
+}
+
+int hqc_tune_set(int param_id, size_t count, int tile, int grid) {
+  if (!pid_bit(param_id) || count == 0 || count > HQC_MAX_COUNT) return HQC_EINVAL;
+  const bool erase = tile == 0 && grid == 0;
+  if (!erase && (tile < 1 || tile > 64 || grid < 1)) return HQC_EINVAL;
+  const auto key = std::make_tuple(device_or_none(), param_id, count_bucket(count));
+  std::lock_guard<std::mutex> lk(g_tuned.mu);
+  if (erase)
+    g_tuned.table.erase(key);
+  else
+    g_tuned.table[key] = std::make_pair(tile, grid);
+  return HQC_OK;
+}
+
+int hqc_tune_get(int param_id, size_t count, int *tile, int *grid) {
+  if (!pid_bit(param_id) || !tile || !grid || count == 0 || count > HQC_MAX_COUNT)
+    return HQC_EINVAL;
+  if (!tuned_lookup(param_id, count, tile, grid)) *tile = *grid = 0;
+  return HQC_OK;
+}
+
+void hqc_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tuned.mu);
+  g_tuned.table.clear();
 }
 
 }  // extern "C"

@@ -1,0 +1,168 @@
+// hqc_tune.hip -- launch-configuration autotuner of the decryption kernel
+// (hqc_autotune_decrypt in include/hqc_gpu.h).
+//
+// Candidates are (tile, grid) pairs: tiles of 1 .. 64 ciphertexts (the
+// tile also picks the Reed-Solomon mapping, two lanes per word up to 32)
+// and grids of 1/2 .. 3/2 of the occupancy grid, or one tile per workgroup
+// when a batch has fewer tiles than half that grid.  Each is launched once
+// untimed and its messages compared byte for byte with those of the
+// built-in default; then `reps` rounds time every candidate once per round
+// with HIP events on the caller's stream (so drift during the search hits
+// all alike), and the median decides.  Inputs are random words and random
+// support indices: the kernels' time does not depend on the data, so any
+// input is representative.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "hqc_gpu.h"
+
+namespace {
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) of seed + (i + 1) * golden
+__device__ __forceinline__ uint64_t mix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_words(uint64_t *p, size_t n, uint64_t seed) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = mix64(seed, i);
+}
+
+__global__ void fill_indices(uint32_t *y, size_t n, uint32_t mod, uint64_t seed) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (uint32_t)(mix64(seed, i) % mod);
+}
+
+struct Buffers {
+  uint64_t *u = nullptr, *v = nullptr;
+  uint32_t *y = nullptr;
+  uint8_t *m = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Buffers() {
+    (void)hipFree(u);
+    (void)hipFree(v);
+    (void)hipFree(y);
+    (void)hipFree(m);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *stream,
+                                    hqc_tune_report_t *out) {
+  if (!out || reps < 1 || count == 0) return HQC_EINVAL;
+  hqc_sizes_t sz;
+  if (hqc_sizes(param_id, &sz) != HQC_OK) return HQC_EINVAL;
+  if (count > ((size_t)1 << 20)) return HQC_ERANGE;
+  const int full = hqc_default_grid(param_id);
+  if (full < 0) return full;
+  if (full == 0) return HQC_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+
+  Buffers B;
+  const size_t nu = count * (size_t)sz.u_words, nv = count * (size_t)sz.v_words;
+  const size_t ny = count * (size_t)sz.w, nm = count * (size_t)sz.k;
+  if (hipMalloc(&B.u, nu * 8) != hipSuccess || hipMalloc(&B.v, nv * 8) != hipSuccess ||
+      hipMalloc(&B.y, ny * 4) != hipSuccess || hipMalloc(&B.m, nm) != hipSuccess) {
+    (void)hipGetLastError();
+    return HQC_ENOMEM;
+  }
+  if (hipEventCreate(&B.a) != hipSuccess || hipEventCreate(&B.b) != hipSuccess) return HQC_EHIP;
+  hipLaunchKernelGGL(fill_words, dim3(1024), dim3(256), 0, st, B.u, nu, 0x7E57ull + param_id);
+  hipLaunchKernelGGL(fill_words, dim3(1024), dim3(256), 0, st, B.v, nv, 0x7E58ull + param_id);
+  hipLaunchKernelGGL(fill_indices, dim3(1024), dim3(256), 0, st, B.y, ny, (uint32_t)sz.n,
+                     0x7E59ull + param_id);
+  if (hipGetLastError() != hipSuccess) return HQC_EHIP;
+
+  // the built-in default first: the occupancy grid and enough tiles for it
+  const int h_tile = (int)std::min<size_t>(64, std::max<size_t>(1, (count + full - 1) / full));
+  std::vector<std::pair<int, int>> cand{{h_tile, full}};
+  const int tiles[] = {1, 2, 4, 8, 16, 24, 32, 40, 48, 64};
+  const int gnum[] = {2, 3, 4, 5, 6};  // grid = full * gnum / 4
+  auto add = [&](int t, int grid) {
+    if (std::find(cand.begin(), cand.end(), std::make_pair(t, grid)) == cand.end())
+      cand.emplace_back(t, grid);
+  };
+  for (int t : tiles) {
+    const size_t ntiles = (count + (size_t)t - 1) / (size_t)t;
+    for (int g : gnum) {
+      const int grid = std::max(1, full * g / 4);
+      if ((size_t)grid <= ntiles) add(t, grid);  // a larger grid would be clipped
+    }
+    // fewer tiles than half the occupancy grid: one tile per workgroup
+    if (ntiles < (size_t)std::max(1, full / 2)) add(t, (int)ntiles);
+  }
+
+  std::vector<uint8_t> ref(nm), got(nm);
+  std::vector<hqc_params_t> par(cand.size());
+  int identical = 1;
+  for (size_t c = 0; c < cand.size(); ++c) {
+    hqc_params_t &p = par[c];
+    std::memset(&p, 0, sizeof p);
+    p.param_id = param_id;
+    p.stream = stream;
+    p.tile = cand[c].first;
+    p.grid = cand[c].second;
+    const int rc = hqc_decrypt_batch(&p, B.u, B.v, B.y, B.m, count);
+    if (rc != HQC_OK) return rc;
+    if (hipMemcpyAsync(got.data(), B.m, nm, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return HQC_EHIP;
+    if (c == 0)
+      ref.swap(got);
+    else if (std::memcmp(ref.data(), got.data(), nm) != 0)
+      identical = 0;
+  }
+  // rounds over all candidates, so that clock and temperature drift during
+  // the search affect every candidate alike; a few untimed launches first
+  for (int r = 0; r < 3; ++r) {
+    const int rc = hqc_decrypt_batch(&par[0], B.u, B.v, B.y, B.m, count);
+    if (rc != HQC_OK) return rc;
+  }
+  std::vector<std::vector<float>> t(cand.size(), std::vector<float>(reps));
+  for (int r = 0; r < reps; ++r)
+    for (size_t c = 0; c < cand.size(); ++c) {
+      if (hipEventRecord(B.a, st) != hipSuccess) return HQC_EHIP;
+      const int rc = hqc_decrypt_batch(&par[c], B.u, B.v, B.y, B.m, count);
+      if (rc != HQC_OK) return rc;
+      if (hipEventRecord(B.b, st) != hipSuccess || hipEventSynchronize(B.b) != hipSuccess ||
+          hipEventElapsedTime(&t[c][r], B.a, B.b) != hipSuccess)
+        return HQC_EHIP;
+    }
+  std::vector<float> med(cand.size());
+  for (size_t c = 0; c < cand.size(); ++c) {
+    std::nth_element(t[c].begin(), t[c].begin() + reps / 2, t[c].end());
+    med[c] = t[c][reps / 2];
+  }
+  // the default stays unless a candidate beats it by more than 1 % (noise)
+  size_t best = (size_t)(std::min_element(med.begin(), med.end()) - med.begin());
+  if (med[best] > 0.99f * med[0]) best = 0;
+  // a configuration that changed the messages is never stored
+  if (identical) {
+    const int rc = hqc_tune_set(param_id, count, cand[best].first, cand[best].second);
+    if (rc != HQC_OK) return rc;
+  }
+  std::memset(out, 0, sizeof *out);
+  out->param_id = param_id;
+  out->count = count;
+  out->tile = cand[best].first;
+  out->grid = cand[best].second;
+  out->ms = med[best];
+  out->heuristic_tile = cand[0].first;
+  out->heuristic_grid = cand[0].second;
+  out->heuristic_ms = med[0];
+  out->candidates = (int32_t)cand.size();
+  out->identical = identical;
+  return HQC_OK;
+}

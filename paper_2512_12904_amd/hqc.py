@@ -31,7 +31,8 @@ EXPORTS = (
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
     "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
     "hqc_kem_decaps_batch", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
-    "hqc_ring_mul_batch",
+    "hqc_ring_mul_batch", "hqc_autotune_decrypt", "hqc_tune_set", "hqc_tune_get",
+    "hqc_tune_clear",
 )
 
 
@@ -54,6 +55,14 @@ class Params(ctypes.Structure):
     _fields_ = [("param_id", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("grid", ctypes.c_int32),
                 ("tile", ctypes.c_int32)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("param_id", ctypes.c_int32), ("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("heuristic_tile", ctypes.c_int32),
+                ("heuristic_grid", ctypes.c_int32), ("heuristic_ms", ctypes.c_float),
+                ("candidates", ctypes.c_int32), ("identical", ctypes.c_int32),
+                ("count", ctypes.c_uint64)]
 
 
 class Segment(ctypes.Structure):
@@ -105,6 +114,13 @@ def lib():
                                          vp, sz, sz]
         L.hqc_shutdown.restype = None
         L.hqc_shutdown.argtypes = []
+        L.hqc_autotune_decrypt.argtypes = [ctypes.c_int, sz, ctypes.c_int, vp,
+                                           ctypes.POINTER(TuneReport)]
+        L.hqc_tune_set.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int]
+        L.hqc_tune_get.argtypes = [ctypes.c_int, sz, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int)]
+        L.hqc_tune_clear.restype = None
+        L.hqc_tune_clear.argtypes = []
         _lib = L
     return _lib
 
@@ -440,3 +456,27 @@ def fixed_weight_batch(pid, draws, out=None, grid=0, stream=None):
                                       _dev(out, torch.int32, "out", (count, nd)), count)
     _check(rc, "hqc_fixed_weight_batch")
     return out
+
+
+def autotune_decrypt(pid, count, reps=5, stream=None):
+    """Time the decryption kernel's (tile, grid) candidates on count random
+    ciphertexts and store the fastest in the library's table (see
+    hqc_autotune_decrypt); returns the report as a dict."""
+    r = TuneReport()
+    _check(lib().hqc_autotune_decrypt(pid, count, reps, _stream(stream), ctypes.byref(r)),
+           "hqc_autotune_decrypt")
+    return {f: getattr(r, f) for f, _ in TuneReport._fields_}
+
+
+def tune_set(pid, count, tile, grid):
+    _check(lib().hqc_tune_set(pid, count, tile, grid), "hqc_tune_set")
+
+
+def tune_get(pid, count):
+    t, g = ctypes.c_int(), ctypes.c_int()
+    _check(lib().hqc_tune_get(pid, count, ctypes.byref(t), ctypes.byref(g)), "hqc_tune_get")
+    return t.value, g.value
+
+
+def tune_clear():
+    lib().hqc_tune_clear()

@@ -1,0 +1,46 @@
+"""The autotuner on the GPU: every candidate configuration gives the same
+messages, the chosen one lands in the table and is used by default launches,
+and decryption under it still matches the checker."""
+import numpy as np
+import pytest
+
+from tests import datasets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_autotune_then_default_launch_matches_checker(pid):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc
+    print("case: autotune pid=%d" % pid, flush=True)
+    hqc.tune_clear()
+    count = 4096
+    r = hqc.autotune_decrypt(pid, count, reps=2)
+    assert r["identical"] == 1 and r["count"] == count and r["candidates"] >= 1
+    assert 1 <= r["tile"] <= 64 and r["grid"] >= 1
+    assert r["ms"] <= r["heuristic_ms"] + 1e-6
+    assert hqc.tune_get(pid, count) == (r["tile"], r["grid"])
+    d = datasets.pke(pid, count, 0x7A0 + pid)
+    dev = "cuda"
+    u = torch.from_numpy(d["u"].view(np.int64)).to(dev)
+    v = torch.from_numpy(d["v"].view(np.int64)).to(dev)
+    y = torch.from_numpy(d["y"].view(np.int32)).to(dev)
+    got = hqc.decrypt_batch(pid, u, v, y)  # grid = tile = 0: the tuned entry
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), d["m"])
+    hqc.tune_clear()
+
+
+def test_autotune_rejects_bad_arguments():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc
+    for args in [(2, 100, 2), (1, 0, 2), (1, 100, 0)]:
+        with pytest.raises(hqc.HqcError):
+            hqc.autotune_decrypt(*args)
+    with pytest.raises(hqc.HqcError):
+        hqc.autotune_decrypt(1, (1 << 20) + 1, 1)
