@@ -382,16 +382,18 @@ constexpr GfPow make_gf_pow() {
 }
 
 // syndrome rows: byte t of dword q of row (j, b) is alpha^(b + i j) for the
-// syndrome index i = 4q + t + 1 <= NS.  HQC-1 and HQC-3 keep all 2 delta
-// syndromes (one lane per word computes them all, a lane pair uses the
-// first delta); HQC-5 always decodes on lane pairs and keeps delta.
-template <int ID> struct SynShape {
-  static constexpr int NS = ID == 5 ? Geo<ID>::TD / 2 : Geo<ID>::TD;
+// syndrome index i = 4q + t + 1 <= NS.  The one-lane form computes all
+// 2 delta syndromes (NS = 2 delta), the lane-pair form the first delta in
+// each half (NS = delta); each form has its own table so that a row is one
+// contiguous block of scalar loads.
+template <int ID, int NS> struct SynShape {
   static constexpr int Q = (NS + 3) / 4;
   using T = BitRows<Geo<ID>::n1, Q>;
 };
-template <int ID> constexpr typename SynShape<ID>::T make_syn_rows() {
-  using Sh = SynShape<ID>;
+template <int ID> using SynLane = SynShape<ID, Geo<ID>::TD>;
+template <int ID> using SynPair = SynShape<ID, Geo<ID>::TD / 2>;
+template <int ID, int NS> constexpr typename SynShape<ID, NS>::T make_syn_rows() {
+  using Sh = SynShape<ID, NS>;
   typename Sh::T t{};
   const GfPow g = make_gf_pow();
   for (int j = 0; j < Geo<ID>::n1; ++j)
@@ -400,7 +402,7 @@ template <int ID> constexpr typename SynShape<ID>::T make_syn_rows() {
         uint32_t w = 0;
         for (int u = 0; u < 4; ++u) {
           const int i = 4 * q + u + 1;
-          if (i <= Sh::NS) w |= (uint32_t)g.e[(b + i * j) % 255] << (8 * u);
+          if (i <= NS) w |= (uint32_t)g.e[(b + i * j) % 255] << (8 * u);
         }
         t.r[j][b][q] = w;
       }
@@ -431,17 +433,25 @@ template <int ID> constexpr typename EvalShape<ID>::T make_eval_rows() {
   return t;
 }
 
-__constant__ SynShape<1>::T kSyn1 = make_syn_rows<1>();
-__constant__ SynShape<3>::T kSyn3 = make_syn_rows<3>();
-__constant__ SynShape<5>::T kSyn5 = make_syn_rows<5>();
+// (HQC-5 always decodes on lane pairs: no one-lane table)
+__constant__ SynLane<1>::T kSynL1 = make_syn_rows<1, Geo<1>::TD>();
+__constant__ SynLane<3>::T kSynL3 = make_syn_rows<3, Geo<3>::TD>();
+__constant__ SynPair<1>::T kSynP1 = make_syn_rows<1, Geo<1>::TD / 2>();
+__constant__ SynPair<3>::T kSynP3 = make_syn_rows<3, Geo<3>::TD / 2>();
+__constant__ SynPair<5>::T kSynP5 = make_syn_rows<5, Geo<5>::TD / 2>();
 __constant__ EvalShape<1>::T kEval1 = make_eval_rows<1>();
 __constant__ EvalShape<3>::T kEval3 = make_eval_rows<3>();
 __constant__ EvalShape<5>::T kEval5 = make_eval_rows<5>();
 
-template <int ID> __device__ __forceinline__ const typename SynShape<ID>::T &syn_rows() {
-  if constexpr (ID == 1) return kSyn1;
-  else if constexpr (ID == 3) return kSyn3;
-  else return kSyn5;
+template <int ID> __device__ __forceinline__ const typename SynLane<ID>::T &syn_rows_lane() {
+  static_assert(ID != 5, "HQC-5 decodes on lane pairs");
+  if constexpr (ID == 1) return kSynL1;
+  else return kSynL3;
+}
+template <int ID> __device__ __forceinline__ const typename SynPair<ID>::T &syn_rows_pair() {
+  if constexpr (ID == 1) return kSynP1;
+  else if constexpr (ID == 3) return kSynP3;
+  else return kSynP5;
 }
 template <int ID> __device__ __forceinline__ const typename EvalShape<ID>::T &eval_rows() {
   if constexpr (ID == 1) return kEval1;
@@ -587,11 +597,11 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 
   // S6: S_i = sum_j c_j alpha^(i j), i = 1 .. TD; byte i - 1 of sa (four to
   // a dword) is S_i
-  uint32_t sa[SynShape<ID>::Q];
+  uint32_t sa[SynLane<ID>::Q];
 #pragma unroll
-  for (int q = 0; q < SynShape<ID>::Q; ++q) sa[q] = 0;
+  for (int q = 0; q < SynLane<ID>::Q; ++q) sa[q] = 0;
 #pragma unroll 1
-  for (int j = 0; j < G::n1; ++j) add_rows(sa, (uint32_t)cs[j], syn_rows<ID>().r[j]);
+  for (int j = 0; j < G::n1; ++j) add_rows(sa, (uint32_t)cs[j], syn_rows_lane<ID>().r[j]);
   // S(x) = sum_i S_i x^(i-1) as planes
   uint32_t SP[8][NCA];
 #pragma unroll
@@ -747,7 +757,7 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
       const uint32_t c = cs[j];
       const uint32_t cp = expz(exp4, logz(log4, c) + gj);
       gj = red255(gj + base);
-      add_rows(sa, cp, syn_rows<ID>().r[j]);
+      add_rows(sa, cp, syn_rows_pair<ID>().r[j]);
     }
   }
   // S(x) = sum_i S_i x^(i-1) as planes, in both halves
