@@ -19,17 +19,21 @@
 //      Walsh-Hadamard transform on packed 16-bit pairs in VGPRs, and a
 //      packed 16-bit peak search (magnitude, then smallest index, then
 //      sign); the symbol byte goes to the tile's symbol table in LDS.
-// Then each lane decodes the Reed-Solomon word of one item of the tile
-// (S6-S10): syndromes, Berlekamp-Massey in 2*delta steps, the error
-// evaluator, and Chien search + Forney at the k message positions only (the
-// parity positions never reach m).  GF(2^8) products go through the log and
-// exp tables, which live in two VGPRs per lane (4 bytes each) and are read
-// with ds_bpermute_b32, a crossbar read whose timing does not depend on the
-// index; a zero operand is carried as a log value >= 512 and masked.
+// Then each lane, or each lane pair for tiles of at most 32 items, decodes
+// the Reed-Solomon word of one item of the tile (S6-S10): syndromes as
+// GF(2)-linear bit rows, Berlekamp-Massey in its reformulated form on
+// bit-sliced vectors (2*delta steps), the error evaluator by a Horner
+// scheme on the same planes, and Chien search + Forney at the k message
+// positions only (the parity positions never reach m).  The few products of
+// two variables go through the log and exp tables, held in lanes 0..31 (8
+// bytes per lane) and read with ds_bpermute_b32 from source lanes below 32,
+// so no two lanes reading different entries share an LDS bank; a zero
+// operand is carried as a log value >= 512 and masked.
 //
 // Constant time: loop bounds and branches depend only on the parameter set,
 // the tile size and loop counters; secret values flow only through selects,
-// funnel-shift amounts, uniform LDS window offsets and bpermute indices.
+// bit masks, funnel-shift amounts, uniform LDS window offsets and bpermute
+// indices into 32 source lanes.
 #include "hqc_device.h"
 
 namespace hqc {
