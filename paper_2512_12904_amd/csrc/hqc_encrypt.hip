@@ -338,7 +338,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 }
 
 template <int MODE, int ID>
-__global__ __launch_bounds__(64) void hqc_encrypt_kernel(EncArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 : 3))) void hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
