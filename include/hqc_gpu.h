@@ -239,6 +239,23 @@ int hqc_ring_mul_batch(const hqc_params_t *params, const uint64_t *a, const uint
                        uint64_t *out, uint8_t *path_out, uint32_t threshold, void *workspace,
                        size_t workspace_bytes, size_t count);
 
+/* ---- Intermediates (debugging and stage-by-stage parity) ---------------
+ * Bytes of one item's record for hqc_decrypt_debug (0 for a bad id).  The
+ * record holds, at increasing offsets: the received word v + (u*y) on its
+ * first n1*n2 bits (4*n1*n2/32 bytes, little-endian dwords), the n1 RM
+ * symbols, the syndromes S_1 .. S_2delta, the error locator Lambda
+ * (2 delta + 1 coefficients, multiplied by a nonzero constant: the decoder's
+ * form of Berlekamp-Massey does not normalise it), and the error values at
+ * the k message positions; then zero to three padding bytes. */
+size_t hqc_debug_bytes(int param_id);
+/* hqc_decrypt_batch that also writes each item's record to dbg_out (device,
+ * count * hqc_debug_bytes(param_id) bytes, 4-byte aligned).  The same
+ * kernels run; the records only add stores.  Messages are identical to
+ * hqc_decrypt_batch's.  HQC_EINVAL as there, or for a bad dbg_out or the
+ * per-item launch flag. */
+int hqc_decrypt_debug(const hqc_params_t *params, const uint64_t *u, const uint64_t *v,
+                      const uint32_t *y, uint8_t *m_out, uint8_t *dbg_out, size_t count);
+
 /* Static text for an HQC_* code. */
 const char *hqc_strerror(int code);
 /* hipError_t of the last HQC_EHIP on this thread (0 if none). */

@@ -272,7 +272,7 @@ int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::S
     if (!s.v || !aligned(s.v, 8)) return HQC_EINVAL;
     if (!in_device_allocation(s.u, c * si.u_words * 8)) return HQC_EINVAL;
     if (!in_device_allocation(s.v, c * si.v_words * 8)) return HQC_EINVAL;
-    if (op == hqc::OP_DECRYPT) {
+    if (op == hqc::OP_DECRYPT || op == hqc::OP_DEBUG) {
       if (!s.y || !aligned(s.y, 4) || !in_device_allocation(s.y, c * si.w * 4)) return HQC_EINVAL;
     } else {
       if (!key_ids || !aligned(key_ids, 4) || !in_device_allocation(key_ids, c * 4))
@@ -289,7 +289,7 @@ int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::S
 }
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, const uint32_t *key_ids);
+                 const hqc_keystore_t *ks, const uint32_t *key_ids, uint8_t *dbg = nullptr);
 
 }  // namespace
 
@@ -303,7 +303,7 @@ struct hqc_keystore {
 namespace {
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, const uint32_t *key_ids) {
+                 const hqc_keystore_t *ks, const uint32_t *key_ids, uint8_t *dbg) {
   int rc = check_params(p);
   if (rc) return rc;
   if (!segs || nseg < 1 || nseg > 3) return HQC_EINVAL;
@@ -326,6 +326,7 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
     }
     mask |= (unsigned)pid_bit(segs[i].param_id);
     total += sd.count;
+    sd.dbg = dbg;  // only single-segment debug launches pass one
     a.seg[a.nseg++] = sd;
   }
   if (total > HQC_MAX_COUNT) return HQC_ERANGE;
@@ -367,6 +368,31 @@ int hqc_decrypt_batch(const hqc_params_t *params, const uint64_t *u, const uint6
   s.y = y;
   s.m_out = m_out;
   return run_segments(hqc::OP_DECRYPT, params, &s, 1, nullptr, nullptr);
+}
+
+size_t hqc_debug_bytes(int param_id) {
+  hqc::SetInfo si;
+  return hqc::set_info(param_id, &si) ? si.dbg_bytes : 0;
+}
+
+int hqc_decrypt_debug(const hqc_params_t *params, const uint64_t *u, const uint64_t *v,
+                      const uint32_t *y, uint8_t *m_out, uint8_t *dbg_out, size_t count) {
+  if (!params || (params->flags & HQC_F_PER_ITEM_LAUNCH)) return HQC_EINVAL;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  if (count && (!dbg_out || !aligned(dbg_out, 4) ||
+                !in_device_allocation(dbg_out, count * si.dbg_bytes)))
+    return HQC_EINVAL;
+  hqc_segment_t s;
+  std::memset(&s, 0, sizeof s);
+  s.param_id = params->param_id;
+  s.count = count;
+  s.u = u;
+  s.v = v;
+  s.y = y;
+  s.m_out = m_out;
+  return run_segments(hqc::OP_DEBUG, params, &s, 1, nullptr, nullptr, dbg_out);
 }
 
 int hqc_decode_batch(const hqc_params_t *params, const uint64_t *r, uint8_t *m_out,

@@ -57,6 +57,9 @@ template <int ID> struct Geo {
   static constexpr int A_BYTES =
       (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
+  // debug dump of one item (byte offsets; the record is a whole number of dwords)
+  static constexpr int DBG_SYM = 4 * W32, DBG_S = DBG_SYM + n1, DBG_LAM = DBG_S + TD,
+                       DBG_E = DBG_LAM + TD + 1, DBG_BYTES = (DBG_E + k + 3) / 4 * 4;
   static_assert(NB != 0, "n is not a multiple of 32 for any HQC set");
   static_assert(TD + 1 <= 64 && k <= 64, "lane-level sizes");
   static_assert(n1 * n2 % 64 == 0, "v is a whole number of words");

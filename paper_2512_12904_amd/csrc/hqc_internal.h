@@ -8,7 +8,9 @@
 
 namespace hqc {
 
-enum Op : int { OP_DECRYPT = 0, OP_DECODE = 1, OP_KEYED = 2 };
+// OP_DEBUG is OP_DECRYPT plus stores of each item's intermediates (SegDev::dbg);
+// it is a separate kernel so that the other ops carry none of its code.
+enum Op : int { OP_DECRYPT = 0, OP_DECODE = 1, OP_KEYED = 2, OP_DEBUG = 3 };
 
 // One homogeneous run of items inside a launch.
 struct SegDev {
@@ -19,6 +21,7 @@ struct SegDev {
   const uint32_t *ks_y;     // keyed only: keystore slots of this parameter set
   unsigned long long *ks_bad;  // keyed only: counter of out-of-range key ids
   uint8_t *m;               // count * k
+  uint8_t *dbg;             // NULL, or count * SetInfo::dbg_bytes of intermediates
   uint32_t ks_cap;          // keyed only: slots in ks_y
   uint32_t count;
   uint32_t first;           // index of the segment's first tile in the launch
@@ -39,6 +42,12 @@ struct SetInfo {
   int n, n1, n2, k, delta, w, mult;
   int u_words, v_words;
   size_t lds_bytes;  // dynamic LDS one workgroup needs for this set
+  // per-item intermediates of a debug launch, at these byte offsets: the
+  // received word v + u*y (n1*n2 bits, little-endian dwords), the RM
+  // symbols (n1), the syndromes S_1..S_2delta, Lambda (2 delta + 1
+  // coefficients, times a nonzero constant), the error values at the k
+  // message positions
+  size_t dbg_bytes, dbg_sym, dbg_s, dbg_lam, dbg_e;
 };
 
 bool set_info(int pid, SetInfo *out);

@@ -578,6 +578,15 @@ __device__ __forceinline__ void bm_step(uint32_t (&D)[8][NC], uint32_t (&T)[8][N
   for (int j = 0; j < 8; ++j) shl1(U[j], T[j]);
 }
 
+// element i of a planar vector as a byte (column col and offset off)
+template <int NC>
+__device__ __forceinline__ uint32_t plane_byte(const uint32_t (&P)[8][NC], int col, uint32_t off) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b |= __builtin_amdgcn_ubfe(P[j][col], off, 1) << j;
+  return b;
+}
+
 // Delta = element r of region A (r uniform), as a byte
 template <int NC>
 __device__ __forceinline__ uint32_t elem_byte(const uint32_t (&P)[8][NC], int r) {
@@ -593,7 +602,8 @@ __device__ __forceinline__ uint32_t elem_byte(const uint32_t (&P)[8][NC], int r)
 // ---- S6-S10: Reed-Solomon decode of one item per lane ------------------------
 template <int ID, int OP>
 __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, GfTab exp4, GfTab log4) {
+                                        const uint8_t *cs, GfTab exp4, GfTab log4,
+                                        uint8_t *dbg) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
   constexpr int P = EvalShape<ID>::P;
@@ -606,6 +616,13 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
   for (int q = 0; q < SynLane<ID>::Q; ++q) sa[q] = 0;
 #pragma unroll 1
   for (int j = 0; j < G::n1; ++j) add_rows(sa, (uint32_t)cs[j], syn_rows_lane<ID>().r[j]);
+  if constexpr (OP == OP_DEBUG) {
+    if (dbg) {
+      for (int j = 0; j < G::n1; ++j) dbg[G::DBG_SYM + j] = cs[j];
+#pragma unroll
+      for (int i = 0; i < TD; ++i) dbg[G::DBG_S + i] = (uint8_t)byte_of(sa, i);
+    }
+  }
   // S(x) = sum_i S_i x^(i-1) as planes
   uint32_t SP[8][NCA];
 #pragma unroll
@@ -649,6 +666,13 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
     }
   }
   keep_elems(DC, TD + 1);
+  if constexpr (OP == OP_DEBUG) {
+    if (dbg) {
+#pragma unroll
+      for (int i = 0; i <= TD; ++i)
+        dbg[G::DBG_LAM + i] = (uint8_t)plane_byte(DC, i >> 5, (uint32_t)i & 31u);
+    }
+  }
 
   // S9 (part): Omega = S(x) Lambda(x) mod x^TD, by Horner over Lambda's
   // coefficients: W <- x W + Lambda_i S
@@ -720,6 +744,8 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
     const uint32_t x = red255(tab(log4, omv) + 255u - tab(log4, oddv));
     uint32_t e = tab(exp4, red255(x + 255u - j));
     e = (lamv == 0 && omv != 0 && oddv != 0) ? e : 0u;
+    if constexpr (OP == OP_DEBUG)
+      if (dbg) dbg[G::DBG_E + t] = (uint8_t)e;
     pack |= ((cs[j] ^ e) & 0xFFu) << (8 * (t & 3));
     if ((t & 3) == 3) {
       if (active) ((uint32_t *)(sg.m + (size_t)item * G::k))[t >> 2] = pack;
@@ -736,7 +762,8 @@ __device__ __forceinline__ void rs_lane(const SegDev &sg, uint32_t item, bool ac
 // coefficients 2i + h for the evaluations.
 template <int ID, int OP>
 __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool active,
-                                        const uint8_t *cs, GfTab exp4, GfTab log4) {
+                                        const uint8_t *cs, GfTab exp4, GfTab log4,
+                                        uint8_t *dbg) {
   using G = Geo<ID>;
   constexpr int TD = G::TD;
   constexpr int H = TD / 2;
@@ -762,6 +789,14 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
       const uint32_t cp = expz(exp4, logz(log4, c) + gj);
       gj = red255(gj + base);
       add_rows(sa, cp, syn_rows_pair<ID>().r[j]);
+    }
+    if constexpr (OP == OP_DEBUG) {
+      if (dbg) {
+        if (!hi)
+          for (int j = 0; j < G::n1; ++j) dbg[G::DBG_SYM + j] = cs[j];
+#pragma unroll
+        for (int i = 0; i < H; ++i) dbg[G::DBG_S + (int)base + i] = (uint8_t)byte_of(sa, i);
+      }
     }
   }
   // S(x) = sum_i S_i x^(i-1) as planes, in both halves
@@ -812,6 +847,13 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
 #pragma unroll
     for (int q = 0; q < NC; ++q) C[j][q] = halves(D[j][q]).hi;
   keep_elems(C, TD + 1);
+  if constexpr (OP == OP_DEBUG) {
+    if (dbg && !hi) {
+#pragma unroll
+      for (int i = 0; i <= TD; ++i)
+        dbg[G::DBG_LAM + i] = (uint8_t)plane_byte(C, i >> 5, (uint32_t)i & 31u);
+    }
+  }
 
   // S9 (part): Omega = S(x) Lambda(x) mod x^TD by Horner, W <- x W + Lambda_i S:
   // the lower half over i = H .. 0, the upper half over i = TD + 1 .. H + 1
@@ -885,6 +927,8 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
     const Halves tv = halves(expz(exp4, lw + 255u - (lv.hi & 0xFFu)));
     const bool root = lv.hi < ZL && lv.lo == red255(lv.hi + 255u - j);
     const uint32_t e = root ? (tv.lo ^ tv.hi) : 0u;
+    if constexpr (OP == OP_DEBUG)
+      if (dbg && !hi) dbg[G::DBG_E + t] = (uint8_t)e;
     pack |= ((cs[j] ^ e) & 0xFFu) << (8 * (t & 3));
     if ((t & 3) == 3) {
       if (active && !hi) ((uint32_t *)(sg.m + (size_t)item * G::k))[t >> 2] = pack;
@@ -918,6 +962,11 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
                           (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS), sg, cur + 1,
                           EARLY && it + 1 < nt);
     wave_sync();
+    if (OP == OP_DEBUG && sg.dbg) {  // debug launch: the received word, in item order
+      const uint32_t *rb = lds + G::RB_OFF + gi * G::RB;
+      uint32_t *dst = (uint32_t *)(sg.dbg + (size_t)cur * G::DBG_BYTES);
+      for (int d = lane; d < G::W32; d += 64) dst[d] = rb[d + d / G::BLK];
+    }
     if (!G::COMPACT && !EARLY && it + 1 < nt) prefetch<ID, OP>(sg, cur + 1, regs);
     {
       // the group's blocks, flat index q n1 + b for block b of slot q, are
@@ -957,13 +1006,14 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   if constexpr (OP == OP_KEYED) {
     bad_key = sg.key_ids[item] >= sg.ks_cap;
   }
+  uint8_t *dbg = (OP == OP_DEBUG && sg.dbg && active) ? sg.dbg + (size_t)item * G::DBG_BYTES : nullptr;
   if constexpr (G::COMPACT) {
-    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
+    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
   } else {
     if (pair)
-      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
+      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
     else
-      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4);
+      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
   }
   if constexpr (OP == OP_KEYED) {
     if (active && bad_key && s == lane) {
@@ -1013,7 +1063,10 @@ const void *kernel_for_mask(unsigned mask) {
     case 1: return (const void *)&hqc_kernel<OP, 1>;
     case 2: return (const void *)&hqc_kernel<OP, 2>;
     case 4: return (const void *)&hqc_kernel<OP, 4>;
-    default: return (const void *)&hqc_kernel<OP, 7>;
+    default:
+      // debug launches carry one parameter set: no mixed-set debug kernel
+      if constexpr (OP == OP_DEBUG) return nullptr;
+      else return (const void *)&hqc_kernel<OP, 7>;
   }
 }
 
@@ -1029,6 +1082,11 @@ template <int ID> void fill_info(SetInfo *o) {
   o->u_words = G::U_WORDS;
   o->v_words = G::V_WORDS;
   o->lds_bytes = G::LDS_BYTES;
+  o->dbg_bytes = G::DBG_BYTES;
+  o->dbg_sym = G::DBG_SYM;
+  o->dbg_s = G::DBG_S;
+  o->dbg_lam = G::DBG_LAM;
+  o->dbg_e = G::DBG_E;
 }
 
 }  // namespace
@@ -1047,6 +1105,7 @@ const void *kernel_ptr(int op, unsigned mask) {
   switch (op) {
     case OP_DECRYPT: return kernel_for_mask<OP_DECRYPT>(mask);
     case OP_DECODE: return kernel_for_mask<OP_DECODE>(mask);
+    case OP_DEBUG: return kernel_for_mask<OP_DEBUG>(mask);
     default: return kernel_for_mask<OP_KEYED>(mask);
   }
 }

@@ -14,6 +14,7 @@ Tensor layouts (per item, row-major, on the GPU):
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +33,7 @@ EXPORTS = (
     "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
     "hqc_kem_decaps_batch", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
     "hqc_ring_mul_batch", "hqc_autotune_decrypt", "hqc_tune_set", "hqc_tune_get",
-    "hqc_tune_clear",
+    "hqc_tune_clear", "hqc_debug_bytes", "hqc_decrypt_debug",
 )
 
 
@@ -121,6 +122,9 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int)]
         L.hqc_tune_clear.restype = None
         L.hqc_tune_clear.argtypes = []
+        L.hqc_debug_bytes.restype = ctypes.c_size_t
+        L.hqc_debug_bytes.argtypes = [ctypes.c_int]
+        L.hqc_decrypt_debug.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, sz]
         _lib = L
     return _lib
 
@@ -480,3 +484,31 @@ def tune_get(pid, count):
 
 def tune_clear():
     lib().hqc_tune_clear()
+
+
+def decrypt_debug(pid, u, v, y, flags=0, grid=0, stream=None, tile=0):
+    """decrypt_batch plus each item's intermediates (hqc_decrypt_debug):
+    returns (m, record) with record a dict of numpy arrays: "r" (received
+    word, count x n1*n2/64 uint64), "sym" (RM symbols), "S" (syndromes),
+    "lam" (Lambda times a nonzero constant), "e" (error values at the
+    message positions)."""
+    sz = sizes(pid)
+    count = u.shape[0]
+    nb = lib().hqc_debug_bytes(pid)
+    out = torch.empty((count, sz["k"]), dtype=torch.uint8, device=u.device)
+    rec = torch.zeros((count, nb), dtype=torch.uint8, device=u.device)
+    p = _params(pid, flags, grid, stream, tile)
+    rc = lib().hqc_decrypt_debug(
+        ctypes.byref(p), _dev(u, torch.int64, "u", (count, sz["u_words"])),
+        _dev(v, torch.int64, "v", (count, sz["v_words"])), _dev(y, torch.int32, "y", (count, sz["w"])),
+        _dev(out, torch.uint8, "m", (count, sz["k"])), _dev(rec, torch.uint8, "dbg", (count, nb)), count)
+    _check(rc, "hqc_decrypt_debug")
+    r = rec.cpu().numpy()
+    n1, k, td = sz["n1"], sz["k"], 2 * sz["delta"]
+    o_sym = 8 * sz["v_words"]
+    o_s = o_sym + n1
+    o_l = o_s + td
+    o_e = o_l + td + 1
+    fields = {"r": np.ascontiguousarray(r[:, :o_sym]).view(np.uint64), "sym": r[:, o_sym:o_s],
+              "S": r[:, o_s:o_l], "lam": r[:, o_l:o_e], "e": r[:, o_e:o_e + k]}
+    return out, fields
