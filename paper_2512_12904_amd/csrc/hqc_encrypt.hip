@@ -9,10 +9,11 @@
 // One 64-lane wavefront per item (persistent grid).  Dense operands are
 // staged as a bit-level doubled copy in LDS and multiplied by the sparse
 // operand with the windowed product of Eq. (1) shared with decryption.  The
-// product goes to an LDS buffer, where the sparse addends (x, r1, e) are
-// XORed in one bit per index by a single lane (no bank conflicts, so the
-// secret positions do not change the timing), and the buffer is written out
-// (or compared with a received ciphertext) with coalesced stores.
+// sparse addends (x, r1, e) are XORed into the product registers one bit
+// per index (the owning lane selects it; the register is addressed with the
+// VGPR index mode, so the secret positions never become memory addresses),
+// and the result goes through an LDS buffer to coalesced stores (or is
+// compared with a received ciphertext).
 // The codeword mG: Reed-Solomon parity by a wavefront-wide LFSR (lane j
 // holds register j; GF(2^8) products through the wave-resident log/exp
 // tables), then each output dword of the duplicated RM(1,7) code from its
@@ -158,16 +159,20 @@ __device__ __forceinline__ void sparse_product(const uint32_t *u2,
   product_acc<ID, N>(u2, sh, acc);
 }
 
-// buf ^= sum over the support of X^(index mod n), indices >= limit dropped.
-// One lane XORs one bit per index with an LDS atomic; the dword and the bit
-// are selects (a dropped index XORs 0 into dword 0), so every index costs the
-// same, and a single-lane access has no bank conflict that could depend on
-// the address.  This replaces a product with the constant polynomial 1.
+// acc ^= the lane's R dwords of sum over the support of X^(index mod n),
+// indices >= limit dropped (they add 0 to dword 0).  Lane l holds output
+// dwords l R .. l R + R - 1, so index q touches dword q / 32 of lane
+// (q / 32) / R, register (q / 32) mod R.  Per index, every lane selects the
+// bit (or 0) by comparing its lane number, and the register is addressed
+// with the VGPR index mode: no branch, no memory access, the same
+// instructions whatever the index.  This replaces a product with the
+// constant polynomial 1.
 template <int ID, int W>
-__device__ __forceinline__ void sparse_xor(uint32_t *buf, const uint32_t (&p)[(W + 63) / 64],
-                                           uint32_t limit) {
+__device__ __forceinline__ void sparse_xor(uint32_t (&acc)[Geo<ID>::R],
+                                           const uint32_t (&p)[(W + 63) / 64], uint32_t limit) {
+  using G = Geo<ID>;
   constexpr int NR = (W + 63) / 64;
-  const int lane = lane_id();
+  const uint32_t lane = (uint32_t)lane_id();
   uint32_t ad[NR], bt[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
@@ -182,7 +187,8 @@ __device__ __forceinline__ void sparse_xor(uint32_t *buf, const uint32_t (&p)[(W
 #pragma unroll 1
     for (int l = 0; l < cnt; ++l) {
       const uint32_t a = rdlane(ad[c], l), b = rdlane(bt[c], l);
-      if (lane == 0) atomicXor(&buf[a], b);
+      const uint32_t owner = a / (uint32_t)G::R, slot = a - owner * (uint32_t)G::R;
+      acc[slot] ^= lane == owner ? b : 0u;
     }
   }
 }
@@ -257,9 +263,8 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     load_support<G::w>(a.x + (size_t)item * G::w, ix);
     stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, G::w>(u2, iy, acc);
+    sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
     put_full<ID>(buf, acc);
-    wave_sync();
-    sparse_xor<ID, G::w>(buf, ix, (uint32_t)G::n);
     wave_sync();
     emit<false>(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw, nullptr);
     wave_sync();
@@ -280,9 +285,8 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     // Alg. 1: u = r1 + h*r2
     stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, WR>(u2, ir2, acc);
+    sparse_xor<ID, WR>(acc, ir1, (uint32_t)G::n);
     put_full<ID>(buf, acc);
-    wave_sync();
-    sparse_xor<ID, WR>(buf, ir1, (uint32_t)G::n);
     wave_sync();
     uint32_t diff = emit<CHECK>(buf, G::DW + 1, 2 * G::U_WORDS, a.u_out + item * nw,
                                 a.u_in + item * nw);
@@ -313,6 +317,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     wave_sync();
     stage_dense<ID>(a.s + item * nw, u2);
     sparse_product<ID, WR>(u2, ir2, acc);
+    sparse_xor<ID, WE>(acc, ie, (uint32_t)(G::n1 * G::n2));
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
       const int d = lane * G::R + j;
@@ -325,8 +330,6 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       if (d < G::W32) buf[d] = acc[j] ^ word;
     }
     wave_sync();
-    sparse_xor<ID, WE>(buf, ie, (uint32_t)(G::n1 * G::n2));
-    wave_sync();
     diff |= emit<CHECK>(buf, G::W32, G::W32, a.v_out + item * (size_t)G::V_WORDS,
                         a.v_in + item * (size_t)G::V_WORDS);
     if constexpr (CHECK) {
@@ -338,7 +341,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 }
 
 template <int MODE, int ID>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 : 3))) void hqc_encrypt_kernel(EncArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 : ID == 1 ? 4 : 3))) void hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
