@@ -184,7 +184,7 @@ __device__ __forceinline__ void sparse_xor(uint32_t (&acc)[Geo<ID>::R],
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     const int cnt = W - 64 * c < 64 ? W - 64 * c : 64;
-#pragma unroll 1
+#pragma unroll 4
     for (int l = 0; l < cnt; ++l) {
       const uint32_t a = rdlane(ad[c], l), b = rdlane(bt[c], l);
       const uint32_t owner = a / (uint32_t)G::R, slot = a - owner * (uint32_t)G::R;
