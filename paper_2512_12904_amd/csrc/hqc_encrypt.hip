@@ -14,9 +14,10 @@
 // VGPR index mode, so the secret positions never become memory addresses),
 // and the result goes through an LDS buffer to coalesced stores (or is
 // compared with a received ciphertext).
-// The codeword mG: Reed-Solomon parity by a wavefront-wide LFSR (lane j
-// holds register j; GF(2^8) products through the wave-resident log/exp
-// tables), then each output dword of the duplicated RM(1,7) code from its
+// The codeword mG: Reed-Solomon parity as a GF(2)-linear map of the message
+// bits (lane j sums its parity byte over rows selected by the bits; no
+// table index depends on m), then each output dword of the duplicated
+// RM(1,7) code from its
 // symbol: a 32-entry pattern table for the low five message bits (read with
 // ds_bpermute_b32) and a whole-dword complement for bits 5-7.
 #include "hqc_device.h"
@@ -25,14 +26,21 @@
 namespace hqc {
 namespace {
 
-// log g_j (and g_j != 0) for g(x) = prod_{i=1}^{2d} (x - alpha^i)
-struct RsGenTables {
-  uint8_t lg[3][64];
-  uint8_t nz[3][64];
+// Reed-Solomon parity as a GF(2)-linear map of the message bits: the
+// parity of m is x^(2d) m(x) mod g(x), g(x) = prod_{i=1}^{2d} (x - alpha^i),
+// which is the XOR over the set bits b of the bytes m_t of the parity of the
+// one-bit message alpha^b x^t.  Row (t, b) is that parity, 2d bytes; byte
+// j of it belongs to lane j.  The table is laid out [set][t][b / 4][lane],
+// byte b mod 4 of each dword, so that a lane reads its bytes of four rows
+// with one dword load and a wavefront's load is one contiguous block.
+template <int ID> struct RsRows {
+  static constexpr int K = Set<ID>::k;
+  uint32_t w[2 * K][64];
 };
 
-constexpr RsGenTables make_rs_gen_tables() {
-  RsGenTables t{};
+template <int ID> constexpr RsRows<ID> make_rs_rows() {
+  constexpr int TD = 2 * Set<ID>::delta, K = Set<ID>::k;
+  RsRows<ID> t{};
   uint8_t e[256] = {}, l[256] = {};
   unsigned x = 1;
   for (int i = 0; i < 255; ++i) {
@@ -41,29 +49,42 @@ constexpr RsGenTables make_rs_gen_tables() {
     x <<= 1;
     if (x & 0x100u) x ^= 0x11Du;
   }
-  const int tds[3] = {30, 32, 58};
-  for (int s = 0; s < 3; ++s) {
-    uint8_t g[64] = {};
-    g[0] = 1;
-    for (int i = 1; i <= tds[s]; ++i) {
-      // g <- g * (x + alpha^i)
-      for (int d = i; d >= 0; --d) {
-        uint8_t lo = g[d] ? e[(l[g[d]] + i) % 255] : 0;  // alpha^i * g_d
-        uint8_t hi = d > 0 ? g[d - 1] : 0;               // x * g (coefficient d)
-        g[d] = (uint8_t)(hi ^ lo);
+  auto mul = [&](uint8_t a, uint8_t b2) -> uint8_t {
+    return (a && b2) ? e[(l[a] + l[b2]) % 255] : 0;
+  };
+  uint8_t g[64] = {};  // g(x), monic of degree TD
+  g[0] = 1;
+  for (int i = 1; i <= TD; ++i)
+    for (int d = i; d >= 0; --d) g[d] = (uint8_t)((d > 0 ? g[d - 1] : 0) ^ mul(g[d], e[i % 255]));
+  for (int tt = 0; tt < K; ++tt)
+    for (int b = 0; b < 8; ++b) {
+      // remainder of alpha^b x^(TD + tt) divided by g: long division
+      uint8_t r[64 + 32] = {};
+      r[TD + tt] = (uint8_t)(1u << b);
+      for (int d = TD + tt; d >= TD; --d) {
+        const uint8_t c = r[d];
+        if (!c) continue;
+        for (int j = 0; j <= TD; ++j) r[d - TD + j] ^= mul(c, g[j]);
       }
+      for (int j = 0; j < TD; ++j) t.w[2 * tt + b / 4][j] |= (uint32_t)r[j] << (8 * (b % 4));
     }
-    for (int j = 0; j < 64; ++j) {
-      t.nz[s][j] = (uint8_t)(j < tds[s] && g[j] != 0);
-      t.lg[s][j] = g[j] ? l[g[j]] : 0;
-    }
-  }
   return t;
 }
 
-__constant__ RsGenTables kRsGen = make_rs_gen_tables();
+__constant__ RsRows<1> kRsRows1 = make_rs_rows<1>();
+__constant__ RsRows<3> kRsRows3 = make_rs_rows<3>();
+__constant__ RsRows<5> kRsRows5 = make_rs_rows<5>();
+template <int ID> __device__ __forceinline__ const RsRows<ID> &rs_rows() {
+  if constexpr (ID == 1) return kRsRows1;
+  else if constexpr (ID == 3) return kRsRows3;
+  else return kRsRows5;
+}
 
-template <int ID> constexpr int gen_slot() { return ID == 1 ? 0 : ID == 3 ? 1 : 2; }
+// four bits of a byte (bits 4h .. 4h + 3) as byte masks 0x00 / 0xFF
+__device__ __forceinline__ uint32_t nibble_masks(uint32_t m, int h) {
+  const uint32_t x = (m >> (4 * h)) & 0xFu;
+  return ((x * 0x00204081u) & 0x01010101u) * 0xFFu;
+}
 
 // bit i of pattern(v) = parity(v & i) for the low five bits (i = 0 .. 31)
 __device__ __forceinline__ uint32_t rm_pattern(uint32_t v) {
@@ -225,7 +246,7 @@ __device__ __forceinline__ uint32_t emit(const uint32_t *buf, int ndw, int nout,
 
 template <int ID, int MODE>
 __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32_t *lds,
-                                         GfTab exp4, GfTab log4, uint32_t pat) {
+                                         uint32_t pat) {
   using G = Geo<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
@@ -292,24 +313,22 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
                                 a.u_in + item * nw);
     wave_sync();
 
-    // Reed-Solomon parity of m: x^{2d} m(x) mod g(x), register j in lane j
+    // Reed-Solomon parity of m: x^{2d} m(x) mod g(x); lane j < 2d sums its
+    // bytes of the rows of the set message bits (four bits per dword)
     constexpr int TD = G::TD;
     const uint8_t *mrow = a.m + (size_t)item * G::k;
     const uint32_t mlane = lane < G::k ? (uint32_t)mrow[lane] : 0u;  // byte t of m in lane t
-    const uint32_t lg = kRsGen.lg[gen_slot<ID>()][lane];
-    const uint32_t gnz = kRsGen.nz[gen_slot<ID>()][lane];
-    uint32_t reg = 0;
-#pragma unroll 1
-    for (int t = G::k - 1; t >= 0; --t) {
+    const auto &rows = rs_rows<ID>();
+    uint32_t racc = 0;
+#pragma unroll 4
+    for (int t = 0; t < G::k; ++t) {
       const uint32_t mt = rdlane(mlane, t);
-      const uint32_t fb = (mt ^ rdlane(reg, TD - 1)) & 0xFFu;
-      const uint32_t lfb = tab(log4, fb);
-      uint32_t prod = tab(exp4, red255(lfb + lg));
-      prod = (fb != 0 && gnz) ? prod : 0u;
-      const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((lane > 0 ? lane - 1 : 0) << 2,
-                                                                  (int)reg);
-      reg = lane < TD ? ((lane > 0 ? prev : 0u) ^ prod) : 0u;
+      // truth table 0x6C: S1 ^ (S0 & S2)
+      racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t][lane], racc, nibble_masks(mt, 0), 0x6C);
+      racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t + 1][lane], racc, nibble_masks(mt, 1), 0x6C);
     }
+    racc ^= racc >> 16;
+    const uint32_t reg = (racc ^ (racc >> 8)) & 0xFFu;
     if (lane < TD) sym[lane] = (uint8_t)reg;
     if (lane < G::k) sym[TD + lane] = (uint8_t)mlane;
 
@@ -345,11 +364,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
-  const GfTab exp4 = gf_exp_tab();
-  const GfTab log4 = gf_log_tab();
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
-    run_item<ID, MODE>(a, item, lds, exp4, log4, pat);
+    run_item<ID, MODE>(a, item, lds, pat);
 }
 
 template <int ID> size_t enc_lds() {
