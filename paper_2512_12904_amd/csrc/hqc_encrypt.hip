@@ -249,9 +249,11 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
                                          uint32_t pat) {
   using G = Geo<ID>;
   const int lane = lane_id();
+  // the output staging buffer takes the place of the doubled copy once the
+  // product has read it (a wave_sync orders the two)
   uint32_t *u2 = lds;
-  uint32_t *buf = lds + G::U2;
-  uint8_t *sym = (uint8_t *)(lds + 2 * G::U2);
+  uint32_t *buf = lds;
+  uint8_t *sym = (uint8_t *)(lds + G::U2);
   uint32_t acc[G::R];
   const size_t nw = (size_t)G::U_WORDS;
 
@@ -285,6 +287,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, G::w>(u2, iy, acc);
     sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
+    wave_sync();  // every window of U2 has been read
     put_full<ID>(buf, acc);
     wave_sync();
     emit<false>(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw, nullptr);
@@ -307,6 +310,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, WR>(u2, ir2, acc);
     sparse_xor<ID, WR>(acc, ir1, (uint32_t)G::n);
+    wave_sync();  // every window of U2 has been read
     put_full<ID>(buf, acc);
     wave_sync();
     uint32_t diff = emit<CHECK>(buf, G::DW + 1, 2 * G::U_WORDS, a.u_out + item * nw,
@@ -337,6 +341,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     stage_dense<ID>(a.s + item * nw, u2);
     sparse_product<ID, WR>(u2, ir2, acc);
     sparse_xor<ID, WE>(acc, ie, (uint32_t)(G::n1 * G::n2));
+    wave_sync();  // every window of U2 has been read
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
       const int d = lane * G::R + j;
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 
 
 template <int ID> size_t enc_lds() {
   using G = Geo<ID>;
-  return sizeof(uint32_t) * 2 * G::U2 + ((G::n1 + 63) / 64) * 64;
+  return sizeof(uint32_t) * G::U2 + ((G::n1 + 63) / 64) * 64;
 }
 
 }  // namespace
