@@ -103,7 +103,7 @@ __device__ __forceinline__ void rho_pi(const L64 (&A)[25], L64 (&B)[25],
 }
 
 __device__ __forceinline__ void keccak_f1600(L64 (&A)[25]) {
-#pragma unroll 1
+#pragma unroll 4
   for (int ir = 0; ir < 24; ++ir) {
     // theta
     L64 C[5];
