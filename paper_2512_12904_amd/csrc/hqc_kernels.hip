@@ -437,6 +437,28 @@ template <int ID> constexpr typename EvalShape<ID>::T make_eval_rows() {
   return t;
 }
 
+// multiplication by alpha^(delta j) as bit rows: byte b % 4 of dword b / 4 of
+// row j is alpha^(delta j + b), the image of bit b of a symbol
+template <int ID> struct PremulRows {
+  uint32_t r[Geo<ID>::n1][2];
+};
+template <int ID> constexpr PremulRows<ID> make_premul_rows() {
+  PremulRows<ID> t{};
+  const GfPow g = make_gf_pow();
+  for (int j = 0; j < Geo<ID>::n1; ++j)
+    for (int b = 0; b < 8; ++b)
+      t.r[j][b / 4] |= (uint32_t)g.e[((Geo<ID>::TD / 2) * j + b) % 255] << (8 * (b % 4));
+  return t;
+}
+__constant__ PremulRows<1> kPremul1 = make_premul_rows<1>();
+__constant__ PremulRows<3> kPremul3 = make_premul_rows<3>();
+__constant__ PremulRows<5> kPremul5 = make_premul_rows<5>();
+template <int ID> __device__ __forceinline__ const PremulRows<ID> &premul_rows() {
+  if constexpr (ID == 1) return kPremul1;
+  else if constexpr (ID == 3) return kPremul3;
+  else return kPremul5;
+}
+
 // (HQC-5 always decodes on lane pairs: no one-lane table)
 __constant__ SynLane<1>::T kSynL1 = make_syn_rows<1, Geo<1>::TD>();
 __constant__ SynLane<3>::T kSynL3 = make_syn_rows<3, Geo<3>::TD>();
@@ -782,12 +804,17 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
   for (int q = 0; q < QP; ++q) sa[q] = 0;
   {
     const uint32_t base = hi ? (uint32_t)H : 0u;
-    uint32_t gj = 0;  // (h H j) mod 255
 #pragma unroll 1
     for (int j = 0; j < G::n1; ++j) {
       const uint32_t c = cs[j];
-      const uint32_t cp = expz(exp4, logz(log4, c) + gj);
-      gj = red255(gj + base);
+      // c alpha^(H j) by bit rows (a constant multiplier is GF(2)-linear)
+      uint32_t m = 0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint32_t row = __builtin_amdgcn_ubfe(premul_rows<ID>().r[j][b >> 2], 8 * (b & 3), 8);
+        m = __builtin_amdgcn_bitop3_b32(row, m, (uint32_t)__builtin_amdgcn_sbfe((int)c, b, 1), 0x6C);
+      }
+      const uint32_t cp = hi ? m : c;
       add_rows(sa, cp, syn_rows_pair<ID>().r[j]);
     }
     if constexpr (OP == OP_DEBUG) {
