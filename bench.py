@@ -359,7 +359,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decryption batch has no cross-GPU step; "
-              "run with --gpus 1 (the sharding design is described in DESIGN.md)", file=sys.stderr)
+              "run with --gpus 1 (each decryption is independent, so a larger job splits into "
+              "per-GPU ranges of the batch with no exchange step)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
