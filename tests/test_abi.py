@@ -108,3 +108,27 @@ def test_kem_workspace_size(gpu_lib):
         # m', flags and the draw rows (2 wr + we words, whole squeeze blocks) of every item
         sz = gpu_lib.sizes(pid)
         assert b >= 1000 * (sz["k"] + 4 + 4 * (2 * sz["wr"] + sz["we"]))
+
+
+def test_debug_record_size_and_argument_checks(gpu_lib):
+    # the record layout: received word, symbols, syndromes, Lambda, error values,
+    # padded to whole dwords
+    import numpy as np
+    L = gpu_lib.lib()
+    assert L.hqc_debug_bytes(2) == 0
+    for pid in (1, 3, 5):
+        sz = gpu_lib.sizes(pid)
+        raw = 8 * sz["v_words"] + sz["n1"] + 2 * sz["delta"] + 2 * sz["delta"] + 1 + sz["k"]
+        assert L.hqc_debug_bytes(pid) == (raw + 3) // 4 * 4
+    buf = np.zeros(1 << 16, np.uint64)
+    ptr = ctypes.c_void_p(buf.ctypes.data)
+    p = gpu_lib.Params(1, 0, None, 0, 0)
+    # host buffers, a missing record buffer and the per-item flag are refused
+    assert L.hqc_decrypt_debug(ctypes.byref(p), ptr, ptr, ptr, ptr, ptr, 1) == gpu_lib.HQC_EINVAL
+    assert L.hqc_decrypt_debug(ctypes.byref(p), ptr, ptr, ptr, ptr, None, 1) == gpu_lib.HQC_EINVAL
+    pi = gpu_lib.Params(1, gpu_lib.F_PER_ITEM_LAUNCH, None, 0, 0)
+    assert L.hqc_decrypt_debug(ctypes.byref(pi), ptr, ptr, ptr, ptr, ptr, 1) == gpu_lib.HQC_EINVAL
+    bad = gpu_lib.Params(2, 0, None, 0, 0)
+    assert L.hqc_decrypt_debug(ctypes.byref(bad), ptr, ptr, ptr, ptr, ptr, 1) == gpu_lib.HQC_EINVAL
+    # count 0 is a no-op
+    assert L.hqc_decrypt_debug(ctypes.byref(p), None, None, None, None, None, 0) == gpu_lib.HQC_OK
