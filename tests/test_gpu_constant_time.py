@@ -30,9 +30,10 @@ from tests import datasets
 
 pytestmark = pytest.mark.gpu
 
-# bounds on |mean(class) / mean(random) - 1|
-HONEST_BOUND = 0.01
-ZERO_BOUND = 0.03
+# bounds on |mean(class) / mean(random) - 1| (measured: about 0.2 % and
+# 1.4 %; a control-flow shortcut would move the means by far more)
+HONEST_BOUND = 0.02
+ZERO_BOUND = 0.05
 
 
 def welch_t(a, b):
