@@ -125,11 +125,19 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
 
 // Floyd's sampling (Bentley & Floyd 1987, positions reflected): W distinct
 // positions in [0, n) from W 32-bit draws a_i.  p_i = i + floor(a_i (n - i)
-// / 2^32); then for i = W-1 down to 0, p_i becomes i if a later p_j equals
-// it.  The three vectors of one encryption (r1, r2, e: wr = we in every set)
-// are sampled in one loop, so that their independent sequential steps
-// overlap.  Position i of vector v is in lane i mod 64 of p[v][i / 64]; the
-// loop length and every access are fixed, the replacement is a select.
+// / 2^32); then for i = W-1 down to 0, p_i becomes i if it equals the final
+// value of a later p_j.  The three vectors of one encryption (r1, r2, e:
+// wr = we in every set) are sampled together.  Position i of vector v is in
+// lane i mod 64 of p[v][i / 64].
+//
+// The steps run over j instead of i: once the final value of p_j is known
+// (p_j, or j if p_j was replaced), one ballot marks every i < j whose
+// original p_i equals it.  Every i < j is marked by the time j = i + 1 is
+// done, so the mark of j is final when j's step starts; the replacement is
+// one select per register at the end.  The marks live in 64-bit lane
+// masks, so the chain from one step to the next is scalar and the compares
+// of a step do not wait on each other.  The loop length and every access
+// are fixed.
 template <int ID, int W>
 __device__ __forceinline__ void floyd3(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
   constexpr int NR = (W + 63) / 64;
@@ -143,29 +151,34 @@ __device__ __forceinline__ void floyd3(const uint32_t *a, uint32_t (&p)[3][(W + 
       const uint32_t ai = a[v * W + (i < W ? i : 0)];
       p[v][c] = i < W ? (uint32_t)i + __umulhi(ai, n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
     }
+  uint64_t dup[3][NR];
 #pragma unroll
-  for (int c = NR - 1; c >= 0; --c) {
-    const int top = W - 64 * c < 64 ? W - 64 * c : 64;
-#pragma unroll 1
-    for (int l = top - 1; l >= 0; --l) {
-      const int i = 64 * c + l;
-      uint32_t pi[3];
-      bool hit[3] = {false, false, false};
+  for (int v = 0; v < 3; ++v)
 #pragma unroll
-      for (int v = 0; v < 3; ++v) pi[v] = rdlane(p[v][c], l);
+    for (int c = 0; c < NR; ++c) dup[v][c] = 0;
 #pragma unroll
-      for (int c2 = c; c2 < NR; ++c2) {
-        const bool later = 64 * c2 + lane > i;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) hit[v] |= later && p[v][c2] == pi[v];
-      }
+  for (int cj = NR - 1; cj >= 0; --cj) {
+    const int top = W - 64 * cj < 64 ? W - 64 * cj : 64;
+#pragma unroll 4
+    for (int lj = top - 1; lj >= 1 - (cj > 0 ? 1 : 0); --lj) {
+      const uint32_t j = (uint32_t)(64 * cj + lj);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        const bool dup = __ballot(hit[v]) != 0ull;
-        p[v][c] = (dup && lane == l) ? (uint32_t)i : p[v][c];
+        const uint32_t pj = rdlane(p[v][cj], lj);
+        const uint32_t fin = ((dup[v][cj] >> lj) & 1ull) ? j : pj;  // final value of p_j
+#pragma unroll
+        for (int c = 0; c <= cj; ++c) {
+          const uint64_t below = c < cj ? ~0ull : ((1ull << lj) - 1ull);  // i < j
+          dup[v][c] |= __ballot(p[v][c] == fin) & below;
+        }
       }
     }
   }
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+      p[v][c] = ((dup[v][c] >> lane) & 1ull) ? (uint32_t)(64 * c + lane) : p[v][c];
 }
 
 // acc = the lane's R dwords of a * (sum over the support of X^index)
