@@ -9,11 +9,13 @@
 // One 64-lane wavefront per item (persistent grid).  Dense operands are
 // staged as a bit-level doubled copy in LDS and multiplied by the sparse
 // operand with the windowed product of Eq. (1) shared with decryption.  The
-// sparse addends (x, r1, e) are XORed into the product registers one bit
-// per index (the owning lane selects it; the register is addressed with the
-// VGPR index mode, so the secret positions never become memory addresses),
-// and the result goes through an LDS buffer to coalesced stores (or is
-// compared with a received ciphertext).
+// sparse addends (x, r1, e) are added one bit per index, either into the
+// product registers (the owning lane selects it; the register is addressed
+// with the VGPR index mode) or into the LDS staging buffer with one atomic
+// XOR per index issued by that index's lane alone; either way the
+// instructions and their timing do not depend on the secret positions.  The
+// result goes through the LDS buffer to coalesced stores (or is compared
+// with a received ciphertext).  Rows of h and s are loaded an item ahead.
 // The codeword mG: Reed-Solomon parity as a GF(2)-linear map of the message
 // bits (lane j sums its parity byte over rows selected by the bits; no
 // table index depends on m), then each output dword of the duplicated
@@ -97,20 +99,28 @@ __device__ __forceinline__ uint32_t rm_pattern(uint32_t v) {
   return p;
 }
 
-// Load the dense polynomial a (dwords 0 .. DW of a row) into registers and
-// write its bit-level doubled copy to U2.
+// registers of one dense row (dwords 0 .. DW, lane-strided)
+template <int ID> constexpr int kDenseRegs = (Geo<ID>::DW + 1 + 63) / 64;
+
+// issue the loads of a dense row (dwords 0 .. DW) into registers
 template <int ID>
-__device__ __forceinline__ void stage_dense(const uint64_t *row, uint32_t *u2) {
+__device__ __forceinline__ void load_dense(const uint64_t *row, uint32_t (&r)[kDenseRegs<ID>]) {
   using G = Geo<ID>;
-  constexpr int NR = (G::DW + 1 + 63) / 64;
   const uint32_t *src = (const uint32_t *)row;
-  uint32_t r[NR];
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
+  for (int c = 0; c < kDenseRegs<ID>; ++c) {
     const int d = lane_id() + 64 * c;
     r[c] = src[d <= G::DW ? d : G::DW];
   }
-  build_doubled_regs<ID, NR>(u2, r);
+}
+
+// Load the dense polynomial a into registers and write its bit-level doubled
+// copy to U2.
+template <int ID>
+__device__ __forceinline__ void stage_dense(const uint64_t *row, uint32_t *u2) {
+  uint32_t r[kDenseRegs<ID>];
+  load_dense<ID>(row, r);
+  build_doubled_regs<ID, kDenseRegs<ID>>(u2, r);
   wave_sync();
 }
 
@@ -138,8 +148,20 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
 // masks, so the chain from one step to the next is scalar and the compares
 // of a step do not wait on each other.  The loop length and every access
 // are fixed.
+template <int W>
+__device__ __forceinline__ void load_draws(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < (W + 63) / 64; ++c) {
+      const int i = 64 * c + lane_id();
+      p[v][c] = a[v * W + (i < W ? i : 0)];
+    }
+}
+
+// p holds the draws (load_draws) on entry and the positions on return
 template <int ID, int W>
-__device__ __forceinline__ void floyd3(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
+__device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
   constexpr int NR = (W + 63) / 64;
   constexpr uint32_t n = (uint32_t)Set<ID>::n;
   const int lane = lane_id();
@@ -148,8 +170,7 @@ __device__ __forceinline__ void floyd3(const uint32_t *a, uint32_t (&p)[3][(W + 
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       const int i = 64 * c + lane;
-      const uint32_t ai = a[v * W + (i < W ? i : 0)];
-      p[v][c] = i < W ? (uint32_t)i + __umulhi(ai, n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
+      p[v][c] = i < W ? (uint32_t)i + __umulhi(p[v][c], n - (uint32_t)i) : 0xFFFFFFFFu;  // never a position
     }
   uint64_t dup[3][NR];
 #pragma unroll
@@ -227,6 +248,37 @@ __device__ __forceinline__ void sparse_xor(uint32_t (&acc)[Geo<ID>::R],
   }
 }
 
+// buf[q / 32] ^= 1 << (q mod 32) for every index q (taken mod n) of the
+// support below limit; indices >= limit are dropped (they XOR 0 into dword
+// 0).  Index 64c + l sits in lane l of p[c]; the lanes take turns, one LDS
+// atomic XOR each with that lane alone active, so no instruction has two
+// lanes that could meet in a bank: the same instructions take the same
+// time whatever the positions.  The caller orders the result before reads
+// with wave_sync.
+template <int ID, int W>
+__device__ __forceinline__ void lds_sparse_xor(uint32_t *buf, const uint32_t (&p)[(W + 63) / 64],
+                                               uint32_t limit) {
+  constexpr int NR = (W + 63) / 64;
+  const int lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const uint32_t q = p[c] % (uint32_t)Set<ID>::n;
+    const bool in = q < limit;
+    uint32_t *const dst = buf + (in ? q >> 5 : 0u);
+    const uint32_t bit = in ? 1u << (q & 31u) : 0u;
+    const int cnt = W - 64 * c < 64 ? W - 64 * c : 64;
+#pragma unroll 8
+    for (int l = 0; l < cnt; ++l) {
+      // an opaque copy of l: the compare stays in the loop instead of being
+      // hoisted out of the item loop as 64 live lane masks
+      int sel = l;
+      asm volatile("" : "+s"(sel));
+      if (lane == sel) __hip_atomic_fetch_xor(dst, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // the lane's R product dwords into buf (bits >= n of the last dword cleared)
 template <int ID>
 __device__ __forceinline__ void put_full(uint32_t *buf, const uint32_t (&acc)[Geo<ID>::R]) {
@@ -257,9 +309,29 @@ __device__ __forceinline__ uint32_t emit(const uint32_t *buf, int ndw, int nout,
   return diff;
 }
 
+// Per-set shape of the encryption kernels, chosen by timing: waves per SIMD
+// (the register budget), whether h and s are loaded an item ahead (two
+// more rows of registers), and whether the sparse additions r1 and e go
+// into the product registers (VGPR index mode, about eight instructions per
+// index) or into the LDS staging buffer (one single-lane atomic XOR each).
+template <int ID> struct EncShape;
+template <> struct EncShape<1> {
+  static constexpr int waves = 4;
+  static constexpr bool pipe = true, reg_xor = true;
+};
+template <> struct EncShape<3> {
+  static constexpr int waves = 4;
+  static constexpr bool pipe = true, reg_xor = false;
+};
+template <> struct EncShape<5> {
+  static constexpr int waves = 1;
+  static constexpr bool pipe = true, reg_xor = false;
+};
+
 template <int ID, int MODE>
-__device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32_t *lds,
-                                         uint32_t pat) {
+__device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32_t next,
+                                         uint32_t *lds, uint32_t pat,
+                                         uint32_t (&hr)[kDenseRegs<ID>]) {
   using G = Geo<ID>;
   const int lane = lane_id();
   // the output staging buffer takes the place of the doubled copy once the
@@ -268,13 +340,15 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   uint32_t *buf = lds;
   uint8_t *sym = (uint8_t *)(lds + G::U2);
   uint32_t acc[G::R];
+  constexpr bool REG_XOR = EncShape<ID>::reg_xor;
   const size_t nw = (size_t)G::U_WORDS;
 
   if constexpr (MODE == ENC_SAMPLE) {
     constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
     static_assert(WR == WE, "one sampling loop for r1, r2 and e");
     uint32_t sp[3][(WR + 63) / 64];
-    floyd3<ID, WR>(a.draws + (size_t)item * a.draw_stride, sp);
+    load_draws<WR>(a.draws + (size_t)item * a.draw_stride, sp);
+    floyd3<ID, WR>(sp);
     const auto &ir1 = sp[0], &ir2 = sp[1], &ie = sp[2];
     uint32_t *out = a.supp_out + (size_t)item * (2 * WR + WE);
 #pragma unroll
@@ -299,14 +373,20 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     load_support<G::w>(a.x + (size_t)item * G::w, ix);
     stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, G::w>(u2, iy, acc);
-    sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
+    if constexpr (REG_XOR) sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
     wave_sync();  // every window of U2 has been read
     put_full<ID>(buf, acc);
+    if constexpr (!REG_XOR) lds_sparse_xor<ID, G::w>(buf, ix, (uint32_t)G::n);
     wave_sync();
     emit<false>(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw, nullptr);
     wave_sync();
     return;
   } else {
+    // encryption.  Pipelined: hr holds this item's h, loaded during the
+    // previous item, and receives the next item's h while s*r2 is computed;
+    // s is loaded while h is staged and the supports are sampled.  Else
+    // each row is loaded where it is used.
+    constexpr bool PIPE = EncShape<ID>::pipe;
     constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
     constexpr bool CHECK = MODE == ENC_CHECK;
     static_assert(WR == WE, "one sampling loop for r1, r2 and e");
@@ -317,14 +397,25 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       load_support<WR>(a.r2 + (size_t)item * WR, ir2);
       load_support<WE>(a.e + (size_t)item * WE, ie);
     } else {
-      floyd3<ID, WR>(a.draws + (size_t)item * a.draw_stride, sp);
+      load_draws<WR>(a.draws + (size_t)item * a.draw_stride, sp);
     }
+    const uint8_t *mrow = a.m + (size_t)item * G::k;
+    const uint32_t mlane = lane < G::k ? (uint32_t)mrow[lane] : 0u;  // byte t of m in lane t
+    uint32_t sr[kDenseRegs<ID>];
+    if constexpr (PIPE) {
+      load_dense<ID>(a.s + item * nw, sr);
+    } else {
+      load_dense<ID>(a.h + item * nw, hr);
+    }
+    build_doubled_regs<ID, kDenseRegs<ID>>(u2, hr);
+    wave_sync();
+    if constexpr (MODE != ENC_ARRAYS) floyd3<ID, WR>(sp);
     // Alg. 1: u = r1 + h*r2
-    stage_dense<ID>(a.h + item * nw, u2);
     sparse_product<ID, WR>(u2, ir2, acc);
-    sparse_xor<ID, WR>(acc, ir1, (uint32_t)G::n);
+    if constexpr (REG_XOR) sparse_xor<ID, WR>(acc, ir1, (uint32_t)G::n);
     wave_sync();  // every window of U2 has been read
     put_full<ID>(buf, acc);
+    if constexpr (!REG_XOR) lds_sparse_xor<ID, WR>(buf, ir1, (uint32_t)G::n);
     wave_sync();
     uint32_t diff = emit<CHECK>(buf, G::DW + 1, 2 * G::U_WORDS, a.u_out + item * nw,
                                 a.u_in + item * nw);
@@ -333,8 +424,6 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     // Reed-Solomon parity of m: x^{2d} m(x) mod g(x); lane j < 2d sums its
     // bytes of the rows of the set message bits (four bits per dword)
     constexpr int TD = G::TD;
-    const uint8_t *mrow = a.m + (size_t)item * G::k;
-    const uint32_t mlane = lane < G::k ? (uint32_t)mrow[lane] : 0u;  // byte t of m in lane t
     const auto &rows = rs_rows<ID>();
     uint32_t racc = 0;
 #pragma unroll 4
@@ -351,13 +440,20 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 
     // v = mG + s*r2 + e, first n1*n2 bits
     wave_sync();
-    stage_dense<ID>(a.s + item * nw, u2);
+    if constexpr (!PIPE) load_dense<ID>(a.s + item * nw, sr);
+    build_doubled_regs<ID, kDenseRegs<ID>>(u2, sr);
+    wave_sync();
+    if (PIPE && next < a.count) load_dense<ID>(a.h + (size_t)next * nw, hr);
     sparse_product<ID, WR>(u2, ir2, acc);
-    sparse_xor<ID, WE>(acc, ie, (uint32_t)(G::n1 * G::n2));
+    if constexpr (REG_XOR) sparse_xor<ID, WE>(acc, ie, (uint32_t)(G::n1 * G::n2));
     wave_sync();  // every window of U2 has been read
+    // an opaque copy of the lane number: the per-register offsets below are
+    // recomputed here rather than hoisted out of the item loop and kept live
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
-      const int d = lane * G::R + j;
+      const int d = ln * G::R + j;
       const int dd = d < G::W32 ? d : 0;
       const int blk = dd / G::BLK, w = (dd % G::BLK) & 3;
       const uint32_t c = sym[blk];
@@ -366,6 +462,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       const uint32_t word = p ^ (0u - flip);
       if (d < G::W32) buf[d] = acc[j] ^ word;
     }
+    if constexpr (!REG_XOR) lds_sparse_xor<ID, WE>(buf, ie, (uint32_t)(G::n1 * G::n2));
     wave_sync();
     diff |= emit<CHECK>(buf, G::W32, G::W32, a.v_out + item * (size_t)G::V_WORDS,
                         a.v_in + item * (size_t)G::V_WORDS);
@@ -378,13 +475,16 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 }
 
 template <int MODE, int ID>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ID == 5 ? 1 : ID == 1 ? 4 : 3))) void hqc_encrypt_kernel(EncArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(EncShape<ID>::waves))) void hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
+  uint32_t hr[kDenseRegs<ID>];
+  constexpr bool ENC = MODE == ENC_ARRAYS || MODE == ENC_STREAM || MODE == ENC_CHECK;
+  if (ENC && EncShape<ID>::pipe && blockIdx.x < a.count) load_dense<ID>(a.h + (size_t)blockIdx.x * G::U_WORDS, hr);
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
-    run_item<ID, MODE>(a, item, lds, pat);
+    run_item<ID, MODE>(a, item, item + gridDim.x, lds, pat, hr);
 }
 
 template <int ID> size_t enc_lds() {

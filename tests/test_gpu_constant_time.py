@@ -1,7 +1,7 @@
-"""Timing check of the decryption kernel against its input data, in the style
-of dudect (Reparaz, Balasch, Verbauwhede, "Dude, is my code constant time?",
-2017): per-launch device times of input classes, interleaved in random
-order.
+"""Timing checks of decryption and decapsulation against their input data,
+in the style of dudect (Reparaz, Balasch, Verbauwhede, "Dude, is my code
+constant time?", 2017): per-launch device times of input classes,
+interleaved in random order.
 
 Classes (count items each):
   zero:   one fixed key, u = 0, v = codewords of random messages (the decoder
@@ -98,3 +98,70 @@ def test_decrypt_time_independent_of_data(pid):
     rel = {n: ts[n].mean() / ts["random"].mean() - 1.0 for n in names}
     assert abs(rel["honest"]) < HONEST_BOUND, rel
     assert abs(rel["zero"]) < ZERO_BOUND, rel
+
+
+@pytest.mark.parametrize("pid", [1, 5])
+def test_decaps_time_independent_of_rejection(pid):
+    """Implicit rejection must not show in the time: decapsulation of honest
+    ciphertexts, of ciphertexts with one bit of v flipped (rejected by the
+    re-encryption check) and of uniformly random ciphertexts (rejected, and
+    past the decoding radius) run the same kernels with the same launch
+    shapes; the selection of m' or sigma is a per-item select."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc
+    print("case: constant-time decapsulation pid=%d" % pid, flush=True)
+    p = datasets.sizes(pid)
+    count, nkeys = 16384, 256
+    dev = "cuda"
+
+    def T(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(dev)
+
+    d = datasets.pke(pid, nkeys, 0xC80 + pid)
+    idx = np.arange(count) % nkeys
+    h, s, y = T(d["h"][idx], np.int64), T(d["s"][idx], np.int64), T(d["y_keys"][idx], np.int32)
+    m = T(synth.words(0xC81 + pid, (count, p["k"] // 8)).view(np.uint8), np.uint8)
+    sigma = T(synth.words(0xC82 + pid, (count, p["k"] // 8)).view(np.uint8), np.uint8)
+    u, v, key = hqc.kem_encaps_batch(pid, h, s, m)
+    vt = v.clone()
+    vt[:, 0] ^= 1
+    classes = {
+        "honest": (u, v),
+        "tampered": (u, vt),
+        "random": (T(synth.words(0xC83 + pid, (count, p["nwords"])), np.int64),
+                   T(synth.words(0xC84 + pid, (count, p["vwords"])), np.int64)),
+    }
+    names = list(classes)
+    ws = torch.empty(hqc.kem_workspace_bytes(pid, count), dtype=torch.uint8, device=dev)
+    out = torch.empty((count, hqc.KEM_KEY_BYTES), dtype=torch.uint8, device=dev)
+
+    def run(n):
+        return hqc.kem_decaps_batch(pid, h, s, y, sigma, *classes[n], key_out=out, workspace=ws)
+
+    for _ in range(3):
+        for n in names:
+            run(n)
+    # the classes are what they claim: honest keys match, tampered ones differ
+    assert torch.equal(run("honest"), key)
+    assert not (run("tampered") == key).all(dim=1).any()
+    torch.cuda.synchronize()
+
+    reps = 60
+    order = np.random.default_rng(pid + 7).permutation(np.repeat(np.arange(len(names)), reps))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in order]
+    for (a, b), c in zip(ev, order):
+        a.record()
+        run(names[c])
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    keep = int(0.95 * reps)
+    ts = {n: np.sort(t[order == i])[:keep] for i, n in enumerate(names)}
+    for n in names:
+        print("pid %d %-8s mean %.4f ms  sd %.4f  t vs honest %.2f" % (
+            pid, n, ts[n].mean(), ts[n].std(), welch_t(ts[n], ts["honest"])), flush=True)
+    rel = {n: ts[n].mean() / ts["honest"].mean() - 1.0 for n in names}
+    assert abs(rel["tampered"]) < HONEST_BOUND, rel
+    assert abs(rel["random"]) < ZERO_BOUND, rel
