@@ -228,10 +228,23 @@ __global__ __launch_bounds__(64) void kem_key_kernel(const uint8_t *m, const uin
       A[i].lo ^= nxt[i].lo;
       A[i].hi ^= nxt[i].hi;
     }
-    if (b + 1 < K::KBLOCKS) {
+    // next block: most lie inside u or inside v (one base, seventeen
+    // loads at fixed offsets); the few that straddle a boundary or hold
+    // the padding take the word-by-word path (b is uniform: scalar branches)
+    const int w0 = (b + 1) * RATE_WORDS;
+    constexpr int WU = K::P, WV = K::P + K::U, WE = K::P + K::U + K::V;
+    if (w0 >= WU && w0 + RATE_WORDS <= WV) {
+      const uint64_t *src = ur + (w0 - WU);
+#pragma unroll
+      for (int i = 0; i < RATE_WORDS; ++i) nxt[i] = ld64(src + i);
+    } else if (w0 >= WV && w0 + RATE_WORDS <= WE) {
+      const uint64_t *src = vr + (w0 - WV);
+#pragma unroll
+      for (int i = 0; i < RATE_WORDS; ++i) nxt[i] = ld64(src + i);
+    } else if (b + 1 < K::KBLOCKS) {
 #pragma unroll
       for (int i = 0; i < RATE_WORDS; ++i)
-        nxt[i] = key_word<ID>((b + 1) * RATE_WORDS + i, pre, alt, use_pre, ur, vr);
+        nxt[i] = key_word<ID>(w0 + i, pre, alt, use_pre, ur, vr);
     }
     keccak_f1600(A);
   }
