@@ -292,40 +292,58 @@ __device__ __forceinline__ void put_full(uint32_t *buf, const uint32_t (&acc)[Ge
 }
 
 // the first ndw dwords of buf to a row (lane-strided, coalesced; dwords
-// ndw .. nout - 1 zero), or (CHECK) the OR of their differences from a row
-template <bool CHECK>
-__device__ __forceinline__ uint32_t emit(const uint32_t *buf, int ndw, int nout, uint64_t *row,
-                                         const uint64_t *cmp) {
+// ndw .. nout - 1 zero)
+__device__ __forceinline__ void emit(const uint32_t *buf, int ndw, int nout, uint64_t *row) {
   uint32_t *dst = (uint32_t *)row;
-  const uint32_t *src = (const uint32_t *)cmp;
+  for (int d = lane_id(); d < nout; d += 64) dst[d] = d < ndw ? buf[d] : 0u;
+}
+
+// the first nout dwords of a row into registers (lane-strided), issued
+// early so that their latency passes while the product runs
+template <int NOUT>
+__device__ __forceinline__ void load_row(const uint64_t *row, uint32_t (&r)[(NOUT + 63) / 64]) {
+  const uint32_t *src = (const uint32_t *)row;
+#pragma unroll
+  for (int c = 0; c < (NOUT + 63) / 64; ++c) {
+    const int d = lane_id() + 64 * c;
+    r[c] = d < NOUT ? src[d] : 0u;
+  }
+}
+
+// OR of the differences between the first ndw dwords of buf (zero above)
+// and the row held by load_row
+template <int NOUT>
+__device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
+                                                const uint32_t (&r)[(NOUT + 63) / 64]) {
   uint32_t diff = 0;
-  for (int d = lane_id(); d < nout; d += 64) {
-    const uint32_t val = d < ndw ? buf[d] : 0u;
-    if constexpr (CHECK)
-      diff |= src[d] ^ val;
-    else
-      dst[d] = val;
+#pragma unroll
+  for (int c = 0; c < (NOUT + 63) / 64; ++c) {
+    const int d = lane_id() + 64 * c;
+    if (d < NOUT) diff |= r[c] ^ (d < ndw ? buf[d] : 0u);
   }
   return diff;
 }
 
 // Per-set shape of the encryption kernels, chosen by timing: waves per SIMD
 // (the register budget), whether h and s are loaded an item ahead (two
-// more rows of registers), and whether the sparse additions r1 and e go
-// into the product registers (VGPR index mode, about eight instructions per
-// index) or into the LDS staging buffer (one single-lane atomic XOR each).
+// more rows of registers), whether the check loads the received u and v
+// before the products that precede their comparison (two more rows; for
+// HQC-3 that would cost a wavefront per SIMD), and whether the sparse
+// additions r1 and e go into the product registers (VGPR index mode, about
+// eight instructions per index) or into the LDS staging buffer (one
+// single-lane atomic XOR each).
 template <int ID> struct EncShape;
 template <> struct EncShape<1> {
   static constexpr int waves = 4;
-  static constexpr bool pipe = true, reg_xor = true;
+  static constexpr bool pipe = true, check_ahead = true, reg_xor = true;
 };
 template <> struct EncShape<3> {
   static constexpr int waves = 4;
-  static constexpr bool pipe = true, reg_xor = false;
+  static constexpr bool pipe = true, check_ahead = false, reg_xor = false;
 };
 template <> struct EncShape<5> {
   static constexpr int waves = 1;
-  static constexpr bool pipe = true, reg_xor = false;
+  static constexpr bool pipe = true, check_ahead = true, reg_xor = false;
 };
 
 template <int ID, int MODE>
@@ -378,7 +396,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     put_full<ID>(buf, acc);
     if constexpr (!REG_XOR) lds_sparse_xor<ID, G::w>(buf, ix, (uint32_t)G::n);
     wave_sync();
-    emit<false>(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw, nullptr);
+    emit(buf, G::DW + 1, 2 * G::U_WORDS, a.s_out + item * nw);
     wave_sync();
     return;
   } else {
@@ -407,6 +425,11 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     } else {
       load_dense<ID>(a.h + item * nw, hr);
     }
+    // the check's received u, loaded while h*r2 is computed
+    constexpr bool AHEAD = CHECK && EncShape<ID>::check_ahead;
+    constexpr int UOUT = 2 * G::U_WORDS;
+    uint32_t cu[CHECK ? (UOUT + 63) / 64 : 1];
+    if constexpr (AHEAD) load_row<UOUT>(a.u_in + item * nw, cu);
     build_doubled_regs<ID, kDenseRegs<ID>>(u2, hr);
     wave_sync();
     if constexpr (MODE != ENC_ARRAYS) floyd3<ID, WR>(sp);
@@ -417,9 +440,17 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     put_full<ID>(buf, acc);
     if constexpr (!REG_XOR) lds_sparse_xor<ID, WR>(buf, ir1, (uint32_t)G::n);
     wave_sync();
-    uint32_t diff = emit<CHECK>(buf, G::DW + 1, 2 * G::U_WORDS, a.u_out + item * nw,
-                                a.u_in + item * nw);
+    uint32_t diff = 0;
+    if constexpr (CHECK) {
+      if constexpr (!AHEAD) load_row<UOUT>(a.u_in + item * nw, cu);
+      diff = compare_row<UOUT>(buf, G::DW + 1, cu);
+    } else
+      emit(buf, G::DW + 1, UOUT, a.u_out + item * nw);
     wave_sync();
+    // the check's received v, loaded while s*r2 is computed (before the next
+    // item's h, so that waiting for it does not wait for those)
+    uint32_t cv[CHECK ? (G::W32 + 63) / 64 : 1];
+    if constexpr (AHEAD) load_row<G::W32>(a.v_in + item * (size_t)G::V_WORDS, cv);
 
     // Reed-Solomon parity of m: x^{2d} m(x) mod g(x); lane j < 2d sums its
     // bytes of the rows of the set message bits (four bits per dword)
@@ -464,8 +495,11 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     }
     if constexpr (!REG_XOR) lds_sparse_xor<ID, WE>(buf, ie, (uint32_t)(G::n1 * G::n2));
     wave_sync();
-    diff |= emit<CHECK>(buf, G::W32, G::W32, a.v_out + item * (size_t)G::V_WORDS,
-                        a.v_in + item * (size_t)G::V_WORDS);
+    if constexpr (CHECK) {
+      if constexpr (!AHEAD) load_row<G::W32>(a.v_in + item * (size_t)G::V_WORDS, cv);
+      diff |= compare_row<G::W32>(buf, G::W32, cv);
+    } else
+      emit(buf, G::W32, G::W32, a.v_out + item * (size_t)G::V_WORDS);
     if constexpr (CHECK) {
       const bool same = __ballot(diff != 0u) == 0ull;
       if (lane == 0) a.ok[item] = same ? 1u : 0u;
