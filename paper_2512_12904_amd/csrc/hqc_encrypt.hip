@@ -145,9 +145,10 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
 // original p_i equals it.  Every i < j is marked by the time j = i + 1 is
 // done, so the mark of j is final when j's step starts; the replacement is
 // one select per register at the end.  The marks live in 64-bit lane
-// masks, so the chain from one step to the next is scalar and the compares
-// of a step do not wait on each other.  The loop length and every access
-// are fixed.
+// masks; a step reads the final value of p_j through a select that takes
+// the mask as its lane condition, so the compares of a step do not wait on
+// each other and no scalar bit test sits in the chain.  The loop length and
+// every access are fixed.
 template <int W>
 __device__ __forceinline__ void load_draws(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
 #pragma unroll
@@ -181,12 +182,15 @@ __device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
   for (int cj = NR - 1; cj >= 0; --cj) {
     const int top = W - 64 * cj < 64 ? W - 64 * cj : 64;
 #pragma unroll 4
-    for (int lj = top - 1; lj >= 1 - (cj > 0 ? 1 : 0); --lj) {
-      const uint32_t j = (uint32_t)(64 * cj + lj);
+    for (int lj = top - 1; lj >= 1 - (cj > 0 ? 1 : 0); --lj) {  // j = 64 cj + lj
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        const uint32_t pj = rdlane(p[v][cj], lj);
-        const uint32_t fin = ((dup[v][cj] >> lj) & 1ull) ? j : pj;  // final value of p_j
+        // final value of p_j: j if marked, else p_j (a per-lane select with
+        // the mark mask as the lane condition, then one lane read: no
+        // scalar bit test in the chain)
+        const uint32_t fv =
+            __builtin_amdgcn_inverse_ballot_w64(dup[v][cj]) ? (uint32_t)(64 * cj + lane) : p[v][cj];
+        const uint32_t fin = rdlane(fv, lj);
 #pragma unroll
         for (int c = 0; c <= cj; ++c) {
           const uint64_t below = c < cj ? ~0ull : ((1ull << lj) - 1ull);  // i < j
@@ -199,7 +203,7 @@ __device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int c = 0; c < NR; ++c)
-      p[v][c] = ((dup[v][c] >> lane) & 1ull) ? (uint32_t)(64 * c + lane) : p[v][c];
+      p[v][c] = __builtin_amdgcn_inverse_ballot_w64(dup[v][c]) ? (uint32_t)(64 * c + lane) : p[v][c];
 }
 
 // acc = the lane's R dwords of a * (sum over the support of X^index)
