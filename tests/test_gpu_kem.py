@@ -139,7 +139,8 @@ def _draw_for(n, i, t):
 @pytest.mark.parametrize("pid", [1, 3, 5])
 def test_fixed_weight_sampling_edge_draws(hqc, pid):
     # crafted draws: no collision, every draw maximal (a chain of collisions),
-    # a position equal to the index of a replaced later position, and random
+    # a position equal to the index of a replaced later position, random, and
+    # two rows of dense collisions
     say("case: Floyd sampling pid=%d" % pid)
     p = datasets.sizes(pid)
     n, wr, we = p["n"], p["wr"], p["we"]
@@ -155,6 +156,16 @@ def test_fixed_weight_sampling_edge_draws(hqc, pid):
             r[off + i] = _draw_for(n, i, t.get(i, 0) if i in t else 50 + 3 * i)
     rows.append(r)
     rows.append(synth.words(0x7E57 + pid, (nd + 1) // 2).view(np.uint32)[:nd])
+    # dense collisions: p_i within i .. i + 2, and p_i anywhere in i .. w - 1
+    # (positions that are indices of earlier-replaced entries: long chains)
+    rng = np.random.default_rng(0xF10 + pid)
+    for span in (3, None):
+        r = np.zeros(nd, np.uint32)
+        for off, w in ((0, wr), (wr, wr), (2 * wr, we)):
+            for i in range(w):
+                t = int(rng.integers(0, span if span else w - i))
+                r[off + i] = _draw_for(n, i, t)
+        rows.append(r)
     draws = np.stack(rows)
     import torch
     out = hqc.fixed_weight_batch(pid, dev(draws))
