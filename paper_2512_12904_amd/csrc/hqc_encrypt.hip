@@ -133,6 +133,19 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
   }
 }
 
+// the 3 W draws of one item (r1, r2, e in turn), draw i of vector v in lane
+// i mod 64 of p[v][i / 64]
+template <int W>
+__device__ __forceinline__ void load_draws(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < (W + 63) / 64; ++c) {
+      const int i = 64 * c + lane_id();
+      p[v][c] = a[v * W + (i < W ? i : 0)];
+    }
+}
+
 // Floyd's sampling (Bentley & Floyd 1987, positions reflected): W distinct
 // positions in [0, n) from W 32-bit draws a_i.  p_i = i + floor(a_i (n - i)
 // / 2^32); then for i = W-1 down to 0, p_i becomes i if it equals the final
@@ -149,17 +162,6 @@ __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg
 // the mask as its lane condition, so the compares of a step do not wait on
 // each other and no scalar bit test sits in the chain.  The loop length and
 // every access are fixed.
-template <int W>
-__device__ __forceinline__ void load_draws(const uint32_t *a, uint32_t (&p)[3][(W + 63) / 64]) {
-#pragma unroll
-  for (int v = 0; v < 3; ++v)
-#pragma unroll
-    for (int c = 0; c < (W + 63) / 64; ++c) {
-      const int i = 64 * c + lane_id();
-      p[v][c] = a[v * W + (i < W ? i : 0)];
-    }
-}
-
 // p holds the draws (load_draws) on entry and the positions on return
 template <int ID, int W>
 __device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
@@ -272,13 +274,8 @@ __device__ __forceinline__ void lds_sparse_xor(uint32_t *buf, const uint32_t (&p
     const uint32_t bit = in ? 1u << (q & 31u) : 0u;
     const int cnt = W - 64 * c < 64 ? W - 64 * c : 64;
 #pragma unroll 8
-    for (int l = 0; l < cnt; ++l) {
-      // an opaque copy of l: the compare stays in the loop instead of being
-      // hoisted out of the item loop as 64 live lane masks
-      int sel = l;
-      asm volatile("" : "+s"(sel));
-      if (lane == sel) __hip_atomic_fetch_xor(dst, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
+    for (int l = 0; l < cnt; ++l)
+      if (lane == l) __hip_atomic_fetch_xor(dst, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   }
   __builtin_amdgcn_sched_barrier(0);
 }
