@@ -49,6 +49,17 @@ def op_model(pid):
     return prod + w32 + rm + 6 * gf
 
 
+def decode_op_model(pid):
+    """Algorithmic integer operations of decoding one received word (RM and
+    RS terms of op_model; no product, no add)."""
+    s = SETS[pid]
+    mult = s["n2"] // 128
+    d = s["delta"]
+    rm = s["n1"] * (128 * mult + 7 * 128 + 2 * 128)
+    gf = 2 * d * (s["n1"] - 1) + 8 * d * d + 2 * d * d + s["n1"] * 2 * d + s["n1"] * 3 * d
+    return rm + 6 * gf
+
+
 def hbm_bytes(pid):
     """u + v + y read, m written, per decryption."""
     s = SETS[pid]
@@ -303,6 +314,62 @@ def pct(xs, q):
     return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
 
 
+def decode_stress_bench(hqc, device, total=1 << 20, reps=5, chunk=65536):
+    """The decoder stress workload: total received words, 50/30/20 % HQC-1/3/5,
+    decoded by one mixed hipGraph launch (hqc_decode_mixed).  The words are
+    made on the device by the library's encryption with h = s = 0, so v = mG
+    + e: codewords of seeded messages plus a weight-we error (the kernel's
+    time does not depend on the data).  Device time per launch from HIP
+    events over reps launches after one untimed one; every message checked."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    counts = {1: total // 2, 3: total * 3 // 10}
+    counts[5] = total - counts[1] - counts[3]
+    items, msgs = [], []
+    for pid, c in counts.items():
+        s = dict(SETS[pid])
+        U = (s["n"] + 63) // 64
+        zero = torch.zeros((min(chunk, c), U), dtype=torch.int64, device=device)
+        r = torch.empty((c, s["n1"] * s["n2"] // 64), dtype=torch.int64, device=device)
+        m_all = torch.empty((c, s["k"]), dtype=torch.uint8, device=device)
+        for a in range(0, c, chunk):
+            b = min(c, a + chunk)
+            m, r1, r2, e = synth.encryptions(0x4E00 + pid, pid, s, b - a, ct_id0=a)
+            t = lambda x, dt: torch.from_numpy(x.view(dt) if x.dtype != np.uint8 else x).to(device)
+            md = t(m, np.uint8)
+            hqc.encrypt_batch(pid, zero[:b - a], zero[:b - a], md, t(r1, np.int32), t(r2, np.int32),
+                              t(e, np.int32), v_out=r[a:b])
+            m_all[a:b] = md
+        items.append({"pid": pid, "r": r})
+        msgs.append(m_all)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    outs = hqc.decode_mixed(items, flags=hqc.F_GRAPH, stream=stream)
+    torch.cuda.synchronize()
+    ok = all(bool(torch.equal(o, m)) for o, m in zip(outs, msgs))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        for it, o in zip(items, outs):
+            it["out"] = o
+        hqc.decode_mixed(items, flags=hqc.F_GRAPH, stream=stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    times = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    ms = sorted(times)[len(times) // 2]
+    ops = sum(decode_op_model(pid) * c for pid, c in counts.items())
+    r = {"words": total, "mix": {"HQC-%d" % p: c for p, c in counts.items()},
+         "ms_median": ms, "words_per_s": total / (ms / 1e3),
+         # can exceed 1: the model counts one op per received bit and per
+         # butterfly, and the RM stage (most of decoding) does two butterflies
+         # per packed 16-bit instruction
+         "op_model_frac": ops / (ms / 1e3) / PEAK_INT_OPS, "all_messages_recovered": ok}
+    del items, outs, msgs
+    torch.cuda.empty_cache()
+    return r
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -409,6 +476,8 @@ def main():
     ap.add_argument("--count", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU checker baseline")
     ap.add_argument("--no-per-item", action="store_true", help="skip the per-launch baseline")
+    ap.add_argument("--no-decode-stress", action="store_true",
+                    help="skip the 1,048,576-word mixed decoding launch")
     ap.add_argument("--sets", default="1,3,5")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of MIB MiB (counter calibration)")
@@ -540,6 +609,10 @@ def main():
     if not args.no_per_item:
         line["per_item_decrypts_per_s"] = main_r["per_item_decrypts_per_s"]
         line["batched_over_per_item"] = main_r["batched_over_per_item"]
+    if not args.no_decode_stress:
+        line["decode_stress"] = decode_stress_bench(hqc, dev)
+        if not line["decode_stress"]["all_messages_recovered"]:
+            print("decoder stress: messages differ from the encoded ones", file=sys.stderr)
     if not args.no_serving:
         line["serving"] = serving_bench(dev, (1e5, 1e6, 1e7), args.serving_seconds)
         line["p99_latency_ms_serving_1e6"] = line["serving"]["1e+06"]["p99_ms"]
