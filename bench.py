@@ -370,6 +370,28 @@ def decode_stress_bench(hqc, device, total=1 << 20, reps=5, chunk=65536):
     return r
 
 
+def gpu_info(device):
+    """Name, architecture, compute units and, where the driver exposes them
+    in sysfs, the graphics clock levels (MHz) of the GPU the bench ran on."""
+    import glob
+    import torch
+    pr = torch.cuda.get_device_properties(device)
+    info = {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""),
+            "compute_units": pr.multi_processor_count,
+            "memory_gib": round(pr.total_memory / 2 ** 30, 1)}
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as f:
+                levels = [ln.split(":", 1)[1].strip() for ln in f if ":" in ln]
+            mhz = [int("".join(ch for ch in lv if ch.isdigit()) or 0) for lv in levels]
+            if mhz:
+                info["sclk_levels_mhz"] = mhz
+                break
+        except (OSError, ValueError):
+            continue
+    return info
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -595,6 +617,7 @@ def main():
                    "launch": "hipGraph, persistent grid, %s" % (
                        "tile %d x grid %d from the autotuner" % (tuned[pid0]["tile"], tuned[pid0]["grid"])
                        if pid0 in tuned else "tile %d / grid %d (0 = library default)" % (TILE, GRID))},
+        "gpu": gpu_info(dev),
         "p50_launch_ms": main_r["ms_p50"],
         "p99_launch_ms": main_r["ms_p99"],
         "per_set": {"HQC-%d" % k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
