@@ -5,7 +5,9 @@
 - 65,536 HQC-3 and 65,536 HQC-5 decryptions, one launch each;
 - 1,048,576 decoder stress words, 50/30/20 HQC-1/3/5, one mixed launch:
   exactly delta RS symbol errors per word (duplicated RM codewords added to
-  delta blocks) plus noise within the RM radius elsewhere.
+  delta blocks) plus noise within the RM radius elsewhere;
+- 65,536 HQC-1 and 65,536 HQC-5 key generations, encryptions and KEM
+  encapsulations / decapsulations.
 
 Every output is compared with the message that was encrypted / encoded
 (ground truth); a sample is also decrypted by the CPU oracle.
@@ -80,3 +82,40 @@ def test_decode_stress_1m_mixed_one_launch(hqc):
     for pid, d in data.items():
         ref = oracle.decode_batch(pid, d["r"][:256])
         assert (outs[[1, 3, 5].index(pid)][:256].cpu().numpy() == ref).all()
+
+
+@pytest.mark.parametrize("pid", [1, 5])
+def test_keygen_encrypt_kem_65536(hqc, pid):
+    """Key generation, encryption and the KEM at 65,536 items with the
+    default persistent grid (the configuration bench.py times): sampled items
+    against the oracle, every item through the GPU round trips."""
+    import torch
+    from paper_2512_12904_amd import synth
+    print("case: keygen/encrypt/KEM 65536 pid=%d" % pid, flush=True)
+    count = 65536
+    p = datasets.sizes(pid)
+    h, x, y = synth.keys(0x6E00 + pid, pid, p, count)
+    ko = np.arange(count, dtype=np.int64)
+    m, r1, r2, e = synth.encryptions(0x6E00 + pid, pid, p, count, key_of=ko)
+    sigma = synth.words(0x6E10 + pid, (count, p["k"] // 8)).view(np.uint8)
+    hd, yd, md = dev(h), dev(y), dev(m)
+    s = hqc.keygen_batch(pid, hd, dev(x), yd)
+    u, v = hqc.encrypt_batch(pid, hd, s, md, dev(r1), dev(r2), dev(e))
+    got = hqc.decrypt_batch(pid, u, v, yd, flags=hqc.F_GRAPH)
+    ku, kv, key = hqc.kem_encaps_batch(pid, hd, s, md)
+    key2 = hqc.kem_decaps_batch(pid, hd, s, yd, dev(sigma), ku, kv)
+    torch.cuda.synchronize()
+    assert torch.equal(got, md)
+    assert torch.equal(key, key2)
+    rng = np.random.default_rng(pid)
+    idx = np.unique(np.concatenate([[0, 1, 2047, 2048, count // 2, count - 1],
+                                    rng.choice(count, 26, replace=False)]))
+    s_h = s.cpu().numpy().view(np.uint64)
+    assert (s_h[idx] == oracle.keygen_batch(pid, h[idx], x[idx], y[idx])).all()
+    u_ref, v_ref = oracle.encrypt_batch(pid, h[idx], s_h[idx], m[idx], r1[idx], r2[idx], e[idx])
+    assert (u.cpu().numpy().view(np.uint64)[idx] == u_ref).all()
+    assert (v.cpu().numpy().view(np.uint64)[idx] == v_ref).all()
+    ru, rv, rkey = oracle.kem_encaps_batch(pid, h[idx], s_h[idx], m[idx])
+    assert (ku.cpu().numpy().view(np.uint64)[idx] == ru).all()
+    assert (kv.cpu().numpy().view(np.uint64)[idx] == rv).all()
+    assert (key.cpu().numpy()[idx] == rkey).all()
