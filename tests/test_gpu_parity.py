@@ -195,3 +195,67 @@ def test_bad_buffer_sizes_rejected(hqc):
     rc = L.hqc_decode_batch(ctypes.byref(prm), ctypes.c_void_p(r.data_ptr()),
                             ctypes.c_void_p(out.data_ptr()), 1 << 20)
     assert rc == hqc.HQC_EINVAL
+
+
+def _bits(words, nbits):
+    return np.unpackbits(words.view(np.uint8), bitorder="little")[:nbits]
+
+
+def _words(bits):
+    return np.packbits(bits, bitorder="little").view(np.uint64)
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_structured_beyond_radius_matches_oracle(hqc, pid):
+    """Words built to sit at the decoders' edges, decoded by the GPU and the
+    oracle: codewords with exactly delta + 1, delta + 2 and 2 delta wrong RS
+    symbols (just past the radius: Berlekamp-Massey ends above degree delta),
+    blocks set to all zeros or all ones, and blocks equidistant from two RM
+    codewords (Hadamard peaks of equal magnitude: the tie rule decides)."""
+    say("case: structured beyond radius pid=%d" % pid)
+    p = datasets.sizes(pid)
+    par = oracle.param(pid)
+    n1, n2, delta = par["n1"], par["n2"], par["delta"]
+    mult = n2 // 128
+    words = n2 // 64
+    rng = np.random.default_rng(0xB7 + pid)
+    rows = []
+    for kind in range(8):
+        for rep in range(8):
+            m = rng.integers(0, 256, p["k"], dtype=np.uint8)
+            r = oracle.code_encode(pid, m).copy()
+            blocks = r.reshape(n1, words)
+            if kind < 3:
+                # exactly delta + 1, delta + 2 or 2 delta blocks replaced by
+                # other RM codewords (each a whole wrong symbol)
+                t = (delta + 1, delta + 2, 2 * delta)[kind]
+                for b in rng.choice(n1, t, replace=False):
+                    cur = oracle.rm_decode(mult, blocks[b])[0]
+                    new = (int(cur) + 1 + int(rng.integers(0, 255))) % 256
+                    blocks[b] = oracle.rm_encode(mult, new)
+            elif kind == 3:
+                blocks[rng.choice(n1, delta + 1, replace=False)] = 0
+            elif kind == 4:
+                blocks[rng.choice(n1, delta + 1, replace=False)] = np.uint64(0xFFFFFFFFFFFFFFFF)
+            else:
+                # ties: a block halfway between the codewords of a and b (half
+                # of the positions where they differ flipped), on 1, delta + 1
+                # or every block
+                t = (1, delta + 1, n1)[kind - 5]
+                for blk in rng.choice(n1, t, replace=False):
+                    a, b = (int(v) for v in rng.choice(256, 2, replace=False))
+                    ca = _bits(oracle.rm_encode(mult, a), n2)
+                    cb = _bits(oracle.rm_encode(mult, b), n2)
+                    diff = np.flatnonzero(ca != cb)
+                    flip = rng.choice(diff, len(diff) // 2, replace=False)
+                    c = ca.copy()
+                    c[flip] ^= 1
+                    blocks[blk] = _words(c)
+            rows.append(r)
+    r = np.stack(rows)
+    got = host(hqc.decode_batch(pid, dev(r)))
+    assert (got == oracle.decode_batch(pid, r)).all()
+    # the same words through decryption with u = 0
+    z = np.zeros((len(rows), p["nwords"]), np.uint64)
+    y = np.tile(np.arange(p["w"], dtype=np.uint32), (len(rows), 1))
+    assert (host(hqc.decrypt_batch(pid, dev(z), dev(r), dev(y))) == got).all()
