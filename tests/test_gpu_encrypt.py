@@ -44,12 +44,18 @@ def test_keygen_encrypt_match_oracle(hqc, pid, count, grid):
     p = datasets.sizes(pid)
     h, x, y = synth.keys(0x900 + pid, pid, p, count)
     x[0, 0] = x[0, 1]  # a repeated index cancels, as in the oracle
+    n = p["n"]
+    x[-1, 2] = n + 11  # indices are taken mod n
+    y[-1, 0] = n
     s_ref = oracle.keygen_batch(pid, h, x, y)
     s_gpu = host(hqc.keygen_batch(pid, dev(h), dev(x), dev(y), grid=grid)).view(np.uint64)
     assert (s_gpu == s_ref).all()
     ko = np.arange(count, dtype=np.int64)
     m, r1, r2, e = synth.encryptions(0x900 + pid, pid, p, count, key_of=ko)
     e[-1, :3] = [0, p["n"] - 1, p["n1"] * p["n2"] - 1]  # edges of the truncation and the ring
+    r1[0, :2] = [n + 5, 5]    # the same position twice (mod n): cancels
+    r2[-1, 1] = r2[-1, 0]     # a repeated index of the product cancels
+    e[0, 3] = n + 7           # taken mod n
     u_ref, v_ref = oracle.encrypt_batch(pid, h, s_ref, m, r1, r2, e, key_of=ko)
     u, v = hqc.encrypt_batch(pid, dev(h), dev(s_ref), dev(m), dev(r1), dev(r2), dev(e), grid=grid)
     assert (host(u).view(np.uint64) == u_ref).all()
