@@ -326,7 +326,9 @@ __device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
 }
 
 // Per-set shape of the encryption kernels, chosen by timing: waves per SIMD
-// (the register budget), whether h and s are loaded an item ahead (two
+// (the register budget; sampled_waves for the kernels that sample the
+// supports from draws: encapsulation and the re-encryption check), whether
+// h and s are loaded an item ahead (two
 // more rows of registers), whether the check loads the received u and v
 // before the products that precede their comparison (two more rows; for
 // HQC-3 that would cost a wavefront per SIMD), and whether the sparse
@@ -335,15 +337,15 @@ __device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
 // single-lane atomic XOR each).
 template <int ID> struct EncShape;
 template <> struct EncShape<1> {
-  static constexpr int waves = 4;
+  static constexpr int waves = 4, sampled_waves = 5;
   static constexpr bool pipe = true, check_ahead = true, reg_xor = true;
 };
 template <> struct EncShape<3> {
-  static constexpr int waves = 4;
+  static constexpr int waves = 4, sampled_waves = 4;
   static constexpr bool pipe = true, check_ahead = false, reg_xor = false;
 };
 template <> struct EncShape<5> {
-  static constexpr int waves = 1;
+  static constexpr int waves = 1, sampled_waves = 1;
   static constexpr bool pipe = true, check_ahead = true, reg_xor = false;
 };
 
@@ -510,7 +512,9 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 }
 
 template <int MODE, int ID>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(EncShape<ID>::waves))) void hqc_encrypt_kernel(EncArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == ENC_STREAM || MODE == ENC_CHECK ? EncShape<ID>::sampled_waves
+                                                                            : EncShape<ID>::waves))) void
+hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];
   using G = Geo<ID>;
   const int lane = lane_id();
