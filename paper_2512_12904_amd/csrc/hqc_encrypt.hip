@@ -114,16 +114,6 @@ __device__ __forceinline__ void load_dense(const uint64_t *row, uint32_t (&r)[kD
   }
 }
 
-// Load the dense polynomial a into registers and write its bit-level doubled
-// copy to U2.
-template <int ID>
-__device__ __forceinline__ void stage_dense(const uint64_t *row, uint32_t *u2) {
-  uint32_t r[kDenseRegs<ID>];
-  load_dense<ID>(row, r);
-  build_doubled_regs<ID, kDenseRegs<ID>>(u2, r);
-  wave_sync();
-}
-
 template <int NIDX>
 __device__ __forceinline__ void load_support(const uint32_t *src, uint32_t (&reg)[(NIDX + 63) / 64]) {
 #pragma unroll
@@ -328,25 +318,25 @@ __device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
 // Per-set shape of the encryption kernels, chosen by timing: waves per SIMD
 // (the register budget; sampled_waves for the kernels that sample the
 // supports from draws: encapsulation and the re-encryption check), whether
-// h and s are loaded an item ahead (two
-// more rows of registers), whether the check loads the received u and v
-// before the products that precede their comparison (two more rows; for
-// HQC-3 that would cost a wavefront per SIMD), and whether the sparse
-// additions r1 and e go into the product registers (VGPR index mode, about
-// eight instructions per index) or into the LDS staging buffer (one
-// single-lane atomic XOR each).
+// h and s are loaded an item ahead in encryption (pipe; two more rows of
+// registers) and h in key generation (keygen_pipe), whether the check
+// loads the received u and v before the products that precede their
+// comparison (two more rows; for HQC-3 that would cost a wavefront per
+// SIMD), and whether the sparse additions r1 and e go into the product
+// registers (VGPR index mode, about eight instructions per index) or into
+// the LDS staging buffer (one single-lane atomic XOR each).
 template <int ID> struct EncShape;
 template <> struct EncShape<1> {
   static constexpr int waves = 4, sampled_waves = 5;
-  static constexpr bool pipe = true, check_ahead = true, reg_xor = true;
+  static constexpr bool pipe = true, keygen_pipe = false, check_ahead = true, reg_xor = true;
 };
 template <> struct EncShape<3> {
   static constexpr int waves = 4, sampled_waves = 4;
-  static constexpr bool pipe = true, check_ahead = false, reg_xor = false;
+  static constexpr bool pipe = true, keygen_pipe = true, check_ahead = false, reg_xor = false;
 };
 template <> struct EncShape<5> {
   static constexpr int waves = 1, sampled_waves = 1;
-  static constexpr bool pipe = true, check_ahead = true, reg_xor = false;
+  static constexpr bool pipe = true, keygen_pipe = true, check_ahead = true, reg_xor = false;
 };
 
 template <int ID, int MODE>
@@ -392,7 +382,13 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     uint32_t iy[NR], ix[NR];
     load_support<G::w>(a.y + (size_t)item * G::w, iy);
     load_support<G::w>(a.x + (size_t)item * G::w, ix);
-    stage_dense<ID>(a.h + item * nw, u2);
+    // hr holds this item's h (loaded during the previous item when
+    // pipelined) and receives the next item's h while h*y is computed
+    constexpr bool KPIPE = EncShape<ID>::keygen_pipe;
+    if constexpr (!KPIPE) load_dense<ID>(a.h + item * nw, hr);
+    build_doubled_regs<ID, kDenseRegs<ID>>(u2, hr);
+    wave_sync();
+    if (KPIPE && next < a.count) load_dense<ID>(a.h + (size_t)next * nw, hr);
     sparse_product<ID, G::w>(u2, iy, acc);
     if constexpr (REG_XOR) sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
     wave_sync();  // every window of U2 has been read
@@ -520,8 +516,9 @@ hqc_encrypt_kernel(EncArgs a) {
   const int lane = lane_id();
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
   uint32_t hr[kDenseRegs<ID>];
-  constexpr bool ENC = MODE == ENC_ARRAYS || MODE == ENC_STREAM || MODE == ENC_CHECK;
-  if (ENC && EncShape<ID>::pipe && blockIdx.x < a.count) load_dense<ID>(a.h + (size_t)blockIdx.x * G::U_WORDS, hr);
+  constexpr bool AHEAD = MODE == ENC_KEYGEN ? EncShape<ID>::keygen_pipe
+                                            : MODE != ENC_SAMPLE && EncShape<ID>::pipe;
+  if (AHEAD && blockIdx.x < a.count) load_dense<ID>(a.h + (size_t)blockIdx.x * G::U_WORDS, hr);
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
     run_item<ID, MODE>(a, item, item + gridDim.x, lds, pat, hr);
 }
