@@ -10,7 +10,7 @@
  * for seed formation and key derivation; Decaps decrypts, re-encrypts,
  * compares and rejects implicitly) but not their byte-level form, and the
  * specification is not available here.  The construction fixed below is
- * this build's reading; it is self-consistent, and its SHAKE256 agrees with
+ * one reading of the paper; it is self-consistent, and its SHAKE256 agrees with
  * an independent implementation (Python's hashlib), but interoperability
  * with the official HQC byte strings is parity unpinned.
  *

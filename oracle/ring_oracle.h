@@ -8,7 +8,7 @@
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
  * calls this code; it shares no source with the GPU path.
  *
- * Dense path (the paper names Toom-Cook; this build uses its two-way case,
+ * Dense path (the paper names Toom-Cook; this oracle uses its two-way case,
  * Karatsuba, over 64-bit words): operands zero-padded to 2^L * M words,
  * M = ceil(U / 2^L), L = hqco_ring_levels(U); a split at h words gives
  *   A = A0 + X^(64h) A1,  P0 = A0 B0,  P1 = A1 B1,  P2 = (A0 + A1)(B0 + B1),
