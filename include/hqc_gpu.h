@@ -101,7 +101,8 @@ typedef struct hqc_segment {
   size_t count;            /* items in this segment */
   const uint64_t *u;       /* decrypt: count * u_words; decode: r, count * v_words */
   const uint64_t *v;       /* decrypt: count * v_words; decode: NULL */
-  const uint32_t *y;       /* decrypt: count * w; decode: NULL */
+  const uint32_t *y;       /* decrypt: count * w; decode: NULL;
+                              hqc_decrypt_mixed_keyed: count key ids */
   uint8_t *m_out;          /* count * k bytes */
 } hqc_segment_t;
 
@@ -155,6 +156,17 @@ int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks
                             const uint64_t *u, const uint64_t *v,
                             const uint32_t *key_ids, uint8_t *m_out, size_t count);
 
+/* Mixed HQC-1/3/5 batch with keys from the keystore, as one persistent
+ * launch (Alg. 2 per item; the serving loop's batches): up to 3 segments,
+ * at most one per parameter set.  In each segment, y holds count uint32 key
+ * ids (device, 4-byte aligned) into that set's slots instead of keys; u, v
+ * and m_out are as for hqc_decrypt_mixed.  Out-of-range ids decrypt to zero
+ * bytes and are counted as in hqc_decrypt_batch_keyed.  Results equal one
+ * hqc_decrypt_batch_keyed call per segment.  HQC_EINVAL for a NULL keystore
+ * or as hqc_decrypt_mixed. */
+int hqc_decrypt_mixed_keyed(const hqc_params_t *params, const hqc_keystore_t *ks,
+                            const hqc_segment_t *segs, int nseg);
+
 /* Key generation, Alg. 3 (the randomness is an input): s[i] = x[i] + h[i]*y[i]
  * in GF(2)[X]/(X^n - 1).  h, s_out: count * u_words; x, y: count * w.
  * Indices are taken mod n; s_out bits >= n are zero. */
@@ -169,6 +181,20 @@ int hqc_keygen_batch(const hqc_params_t *params, const uint64_t *h, const uint32
 int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
                       const uint8_t *m, const uint32_t *r1, const uint32_t *r2,
                       const uint32_t *e, uint64_t *u_out, uint64_t *v_out, size_t count);
+
+/* The concatenated code of Sec. II-A (the mG of Alg. 1) with an optional
+ * symbol-error pattern between the outer and the inner code:
+ *     r_out[i] = the n1 duplicated RM(1,7) blocks of c + sym_err[i],
+ *     c = the systematic RS codeword of m[i] (parity at symbols 0 .. 2 delta - 1,
+ *         m[i][t] at symbol 2 delta + t),
+ * i.e. C.Encode(m[i]) when sym_err is NULL.  A nonzero byte e at symbol j
+ * replaces RM block j by the codeword of c_j + e, so that the block decodes
+ * to a wrong symbol whatever noise within the RM radius is added: the
+ * decoder-stress words are r_out plus such noise.  m: count * k bytes;
+ * sym_err: NULL or count * n1 bytes; r_out: count * v_words words, 8-byte
+ * aligned; all device memory.  params->flags must be 0. */
+int hqc_code_encode_batch(const hqc_params_t *params, const uint8_t *m, const uint8_t *sym_err,
+                          uint64_t *r_out, size_t count);
 
 /* ---- KEM (Sec. II-A: the PKE wrapped by the HHK transform with implicit
  * rejection; domain-separated SHAKE256 for seed formation and key
@@ -244,8 +270,8 @@ int hqc_ring_mul_batch(const hqc_params_t *params, const uint64_t *a, const uint
  * record holds, at increasing offsets: the received word v + (u*y) on its
  * first n1*n2 bits (4*n1*n2/32 bytes, little-endian dwords), the n1 RM
  * symbols, the syndromes S_1 .. S_2delta, the error locator Lambda
- * (2 delta + 1 coefficients, multiplied by a nonzero constant: the decoder's
- * form of Berlekamp-Massey does not normalise it), and the error values at
+ * (2 delta + 1 coefficients, Lambda_0 = 1: Massey's error locator
+ * exactly), and the error values at
  * the k message positions; then zero to three padding bytes. */
 size_t hqc_debug_bytes(int param_id);
 /* hqc_decrypt_batch that also writes each item's record to dbg_out (device,

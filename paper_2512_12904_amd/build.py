@@ -3,6 +3,7 @@
 libhqc_gpu.so   hipcc, gfx950: kernels + C ABI (include/hqc_gpu.h)
 libhqc_synth.so gcc: seeded input generator
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -20,7 +21,7 @@ GPU_HEADERS = [os.path.join(CSRC, "hqc_internal.h"), os.path.join(CSRC, "hqc_int
                os.path.join(ROOT, "include", "hqc_gpu.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
@@ -32,11 +33,27 @@ def hipcc():
     return p
 
 
-def build_gpu(verbose=False):
-    """Compile the HIP library for gfx950 (cross-compiles without a GPU)."""
+def build_gpu(verbose=False, jobs=None):
+    """Compile the HIP library for gfx950 (cross-compiles without a GPU): each
+    source to an object in parallel (the sources share no device symbols),
+    then one shared-library link."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc()] + HIPCC_FLAGS + inc + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, stderr=None if verbose else subprocess.DEVNULL)
+        return obj
+
+    n = jobs or max(1, min(len(GPU_SOURCES), os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(n) as ex:
+        objs = list(ex.map(compile_one, GPU_SOURCES))
     tmp = GPU_SO + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                     "-o", tmp] + GPU_SOURCES
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, stderr=None if verbose else subprocess.DEVNULL)

@@ -255,8 +255,9 @@ int check_params(const hqc_params_t *p) {
   return HQC_OK;
 }
 
-// Validates one segment and fills its device descriptor.
-int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::SegDev *o) {
+// Validates one segment and fills its device descriptor.  Keyed segments
+// carry their key ids (count uint32) in s.y.
+int fill_segment(int op, const hqc_segment_t &s, hqc::SegDev *o) {
   hqc::SetInfo si;
   if (!hqc::set_info(s.param_id, &si) || s.reserved != 0) return HQC_EINVAL;
   if (s.count > HQC_MAX_COUNT) return HQC_ERANGE;
@@ -265,6 +266,7 @@ int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::S
   o->count = (uint32_t)s.count;
   if (s.count == 0) return HQC_OK;
   const size_t c = s.count;
+  const uint32_t *key_ids = op == hqc::OP_KEYED ? s.y : nullptr;
   if (!s.u || !s.m_out || !aligned(s.u, 8) || !aligned(s.m_out, 4)) return HQC_EINVAL;
   if (op == hqc::OP_DECODE) {
     if (!in_device_allocation(s.u, c * si.v_words * 8)) return HQC_EINVAL;
@@ -282,14 +284,14 @@ int fill_segment(int op, const hqc_segment_t &s, const uint32_t *key_ids, hqc::S
   if (!in_device_allocation(s.m_out, c * si.k)) return HQC_EINVAL;
   o->u = s.u;
   o->v = s.v;
-  o->y = s.y;
+  o->y = op == hqc::OP_KEYED ? nullptr : s.y;
   o->key_ids = key_ids;
   o->m = s.m_out;
   return HQC_OK;
 }
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, const uint32_t *key_ids, uint8_t *dbg = nullptr);
+                 const hqc_keystore_t *ks, uint8_t *dbg = nullptr);
 
 }  // namespace
 
@@ -303,10 +305,11 @@ struct hqc_keystore {
 namespace {
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, const uint32_t *key_ids, uint8_t *dbg) {
+                 const hqc_keystore_t *ks, uint8_t *dbg) {
   int rc = check_params(p);
   if (rc) return rc;
   if (!segs || nseg < 1 || nseg > 3) return HQC_EINVAL;
+  if (op == hqc::OP_KEYED && !ks) return HQC_EINVAL;
   hqc::KArgs a;
   std::memset(&a, 0, sizeof a);
   unsigned mask = 0, seen = 0;
@@ -315,7 +318,7 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
     if (seen & (unsigned)pid_bit(segs[i].param_id)) return HQC_EINVAL;  // one per set
     seen |= (unsigned)pid_bit(segs[i].param_id);
     hqc::SegDev sd;
-    rc = fill_segment(op, segs[i], key_ids, &sd);
+    rc = fill_segment(op, segs[i], &sd);
     if (rc) return rc;
     if (sd.count == 0) continue;
     if (op == hqc::OP_KEYED) {
@@ -367,7 +370,7 @@ int hqc_decrypt_batch(const hqc_params_t *params, const uint64_t *u, const uint6
   s.v = v;
   s.y = y;
   s.m_out = m_out;
-  return run_segments(hqc::OP_DECRYPT, params, &s, 1, nullptr, nullptr);
+  return run_segments(hqc::OP_DECRYPT, params, &s, 1, nullptr);
 }
 
 size_t hqc_debug_bytes(int param_id) {
@@ -392,7 +395,7 @@ int hqc_decrypt_debug(const hqc_params_t *params, const uint64_t *u, const uint6
   s.v = v;
   s.y = y;
   s.m_out = m_out;
-  return run_segments(hqc::OP_DEBUG, params, &s, 1, nullptr, nullptr, dbg_out);
+  return run_segments(hqc::OP_DEBUG, params, &s, 1, nullptr, dbg_out);
 }
 
 int hqc_decode_batch(const hqc_params_t *params, const uint64_t *r, uint8_t *m_out,
@@ -404,18 +407,18 @@ int hqc_decode_batch(const hqc_params_t *params, const uint64_t *r, uint8_t *m_o
   s.count = count;
   s.u = r;
   s.m_out = m_out;
-  return run_segments(hqc::OP_DECODE, params, &s, 1, nullptr, nullptr);
+  return run_segments(hqc::OP_DECODE, params, &s, 1, nullptr);
 }
 
 int hqc_decrypt_mixed(const hqc_params_t *params, const hqc_segment_t *segs, int nseg) {
-  return run_segments(hqc::OP_DECRYPT, params, segs, nseg, nullptr, nullptr);
+  return run_segments(hqc::OP_DECRYPT, params, segs, nseg, nullptr);
 }
 
 int hqc_decode_mixed(const hqc_params_t *params, const hqc_segment_t *segs, int nseg) {
   if (segs)
     for (int i = 0; i < nseg && i < 3; ++i)
       if (segs[i].v || segs[i].y) return HQC_EINVAL;
-  return run_segments(hqc::OP_DECODE, params, segs, nseg, nullptr, nullptr);
+  return run_segments(hqc::OP_DECODE, params, segs, nseg, nullptr);
 }
 
 int hqc_keystore_create(hqc_keystore_t **ks, const size_t cap[3]) {
@@ -512,8 +515,15 @@ int hqc_decrypt_batch_keyed(const hqc_params_t *params, const hqc_keystore_t *ks
   s.count = count;
   s.u = u;
   s.v = v;
+  s.y = key_ids;
   s.m_out = m_out;
-  return run_segments(hqc::OP_KEYED, params, &s, 1, ks, key_ids);
+  return run_segments(hqc::OP_KEYED, params, &s, 1, ks);
+}
+
+int hqc_decrypt_mixed_keyed(const hqc_params_t *params, const hqc_keystore_t *ks,
+                            const hqc_segment_t *segs, int nseg) {
+  if (!ks) return HQC_EINVAL;
+  return run_segments(hqc::OP_KEYED, params, segs, nseg, ks);
 }
 
 static int run_encrypt(int mode, const hqc_params_t *params, const hqc::EncArgs &a) {
@@ -596,6 +606,29 @@ int hqc_encrypt_batch(const hqc_params_t *params, const uint64_t *h, const uint6
   a.v_out = v_out;
   a.count = (uint32_t)count;
   return run_encrypt(hqc::ENC_ARRAYS, params, a);
+}
+
+int hqc_code_encode_batch(const hqc_params_t *params, const uint8_t *m, const uint8_t *sym_err,
+                          uint64_t *r_out, size_t count) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  hqc::SetInfo si;
+  if (!hqc::set_info(params->param_id, &si)) return HQC_EINVAL;
+  if (params->flags) return HQC_EINVAL;
+  if (count == 0) return HQC_OK;
+  if (count > HQC_MAX_COUNT) return HQC_ERANGE;
+  const size_t c = count;
+  if (!aligned(r_out, 8) || !in_device_allocation(r_out, c * (size_t)si.v_words * 8) ||
+      !in_device_allocation(m, c * (size_t)si.k))
+    return HQC_EINVAL;
+  if (sym_err && !in_device_allocation(sym_err, c * (size_t)si.n1)) return HQC_EINVAL;
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.m = m;
+  a.sym_err = sym_err;
+  a.v_out = r_out;
+  a.count = (uint32_t)count;
+  return run_encrypt(hqc::ENC_CODE, params, a);
 }
 
 // ---- KEM -------------------------------------------------------------------------
@@ -724,7 +757,7 @@ int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const ui
   sg.v = v;
   sg.y = y;
   sg.m_out = mp;
-  rc = run_segments(hqc::OP_DECRYPT, params, &sg, 1, nullptr, nullptr);
+  rc = run_segments(hqc::OP_DECRYPT, params, &sg, 1, nullptr);
   if (rc) return rc;
   hipError_t e = hqc::launch_kem_draws(pid, mp, draws, (uint32_t)count, st);
   if (e != hipSuccess) return hip_fail(e);

@@ -99,6 +99,39 @@ __device__ __forceinline__ uint32_t rm_pattern(uint32_t v) {
   return p;
 }
 
+// The RS codeword of m into sym[0 .. n1): parity x^(2d) m(x) mod g(x) at
+// symbols 0 .. 2d - 1 (lane j < 2d sums its bytes of the rows of the set
+// message bits, four bits per dword), message byte t at symbol 2d + t.
+// mlane: byte t of m in lane t.  All 64 lanes take part.
+template <int ID>
+__device__ __forceinline__ void rs_codeword(uint32_t mlane, uint8_t *sym) {
+  using G = Geo<ID>;
+  const int lane = lane_id();
+  const auto &rows = rs_rows<ID>();
+  uint32_t racc = 0;
+#pragma unroll 4
+  for (int t = 0; t < G::k; ++t) {
+    const uint32_t mt = rdlane(mlane, t);
+    // truth table 0x6C: S1 ^ (S0 & S2)
+    racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t][lane], racc, nibble_masks(mt, 0), 0x6C);
+    racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t + 1][lane], racc, nibble_masks(mt, 1), 0x6C);
+  }
+  racc ^= racc >> 16;
+  const uint32_t reg = (racc ^ (racc >> 8)) & 0xFFu;
+  if (lane < G::TD) sym[lane] = (uint8_t)reg;
+  if (lane < G::k) sym[G::TD + lane] = (uint8_t)mlane;
+}
+
+// dword w (0 .. 3) of the RM(1,7) codeword of symbol c: pattern(c & 31)
+// from the lane holding it (pat = rm_pattern(lane & 31); all 64 lanes take
+// part), complemented by bit 7 of c and by bits 5, 6 of c where bits 0, 1 of
+// w are set
+__device__ __forceinline__ uint32_t rm_dword(uint32_t c, uint32_t w, uint32_t pat) {
+  const uint32_t p = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((c & 31u) << 2), (int)pat);
+  const uint32_t flip = ((c >> 7) ^ ((c >> 5) & w) ^ ((c >> 6) & (w >> 1))) & 1u;
+  return p ^ (0u - flip);
+}
+
 // registers of one dense row (dwords 0 .. DW, lane-strided)
 template <int ID> constexpr int kDenseRegs = (Geo<ID>::DW + 1 + 63) / 64;
 
@@ -354,7 +387,32 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   constexpr bool REG_XOR = EncShape<ID>::reg_xor;
   const size_t nw = (size_t)G::U_WORDS;
 
-  if constexpr (MODE == ENC_SAMPLE) {
+  if constexpr (MODE == ENC_CODE) {
+    // C.Encode (Sec. II-A) with an optional symbol-error pattern added
+    // between the outer and the inner code: RS codeword of m, + sym_err,
+    // then each RS symbol as a duplicated RM(1,7) block; stored straight
+    // from registers (lane-strided, coalesced)
+    const uint8_t *mrow = a.m + (size_t)item * G::k;
+    const uint32_t mlane = lane < G::k ? (uint32_t)mrow[lane] : 0u;
+    rs_codeword<ID>(mlane, sym);
+    wave_sync();
+    if (a.sym_err) {
+      const uint8_t *er = a.sym_err + (size_t)item * G::n1;
+      for (int j = lane; j < G::n1; j += 64) sym[j] ^= er[j];
+      wave_sync();
+    }
+    uint32_t *dst = (uint32_t *)(a.v_out + (size_t)item * G::V_WORDS);
+#pragma unroll 4
+    for (int i = 0; i < (G::W32 + 63) / 64; ++i) {
+      const int d = lane + 64 * i;
+      const int dd = d < G::W32 ? d : 0;
+      const int blk = dd / G::BLK, w = (dd % G::BLK) & 3;
+      const uint32_t word = rm_dword(sym[blk], (uint32_t)w, pat);
+      if (d < G::W32) dst[d] = word;
+    }
+    wave_sync();  // the symbol table is rewritten by the next item
+    return;
+  } else if constexpr (MODE == ENC_SAMPLE) {
     constexpr int WR = Set<ID>::wr, WE = Set<ID>::we;
     static_assert(WR == WE, "one sampling loop for r1, r2 and e");
     uint32_t sp[3][(WR + 63) / 64];
@@ -451,22 +509,8 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     uint32_t cv[CHECK ? (G::W32 + 63) / 64 : 1];
     if constexpr (AHEAD) load_row<G::W32>(a.v_in + item * (size_t)G::V_WORDS, cv);
 
-    // Reed-Solomon parity of m: x^{2d} m(x) mod g(x); lane j < 2d sums its
-    // bytes of the rows of the set message bits (four bits per dword)
-    constexpr int TD = G::TD;
-    const auto &rows = rs_rows<ID>();
-    uint32_t racc = 0;
-#pragma unroll 4
-    for (int t = 0; t < G::k; ++t) {
-      const uint32_t mt = rdlane(mlane, t);
-      // truth table 0x6C: S1 ^ (S0 & S2)
-      racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t][lane], racc, nibble_masks(mt, 0), 0x6C);
-      racc = __builtin_amdgcn_bitop3_b32(rows.w[2 * t + 1][lane], racc, nibble_masks(mt, 1), 0x6C);
-    }
-    racc ^= racc >> 16;
-    const uint32_t reg = (racc ^ (racc >> 8)) & 0xFFu;
-    if (lane < TD) sym[lane] = (uint8_t)reg;
-    if (lane < G::k) sym[TD + lane] = (uint8_t)mlane;
+    // the RS codeword of m: parity, then the message
+    rs_codeword<ID>(mlane, sym);
 
     // v = mG + s*r2 + e, first n1*n2 bits
     wave_sync();
@@ -486,10 +530,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
       const int d = ln * G::R + j;
       const int dd = d < G::W32 ? d : 0;
       const int blk = dd / G::BLK, w = (dd % G::BLK) & 3;
-      const uint32_t c = sym[blk];
-      const uint32_t p = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((c & 31u) << 2), (int)pat);
-      const uint32_t flip = ((c >> 7) ^ ((c >> 5) & (uint32_t)w) ^ ((c >> 6) & ((uint32_t)w >> 1))) & 1u;
-      const uint32_t word = p ^ (0u - flip);
+      const uint32_t word = rm_dword(sym[blk], (uint32_t)w, pat);
       if (d < G::W32) buf[d] = acc[j] ^ word;
     }
     if constexpr (!REG_XOR) lds_sparse_xor<ID, WE>(buf, ie, (uint32_t)(G::n1 * G::n2));
@@ -517,7 +558,8 @@ hqc_encrypt_kernel(EncArgs a) {
   const uint32_t pat = rm_pattern((uint32_t)lane & 31u);
   uint32_t hr[kDenseRegs<ID>];
   constexpr bool AHEAD = MODE == ENC_KEYGEN ? EncShape<ID>::keygen_pipe
-                                            : MODE != ENC_SAMPLE && EncShape<ID>::pipe;
+                                            : MODE != ENC_SAMPLE && MODE != ENC_CODE &&
+                                                  EncShape<ID>::pipe;
   if (AHEAD && blockIdx.x < a.count) load_dense<ID>(a.h + (size_t)blockIdx.x * G::U_WORDS, hr);
   for (uint32_t item = blockIdx.x; item < a.count; item += gridDim.x)
     run_item<ID, MODE>(a, item, item + gridDim.x, lds, pat, hr);
@@ -544,6 +586,7 @@ const void *encrypt_kernel_ptr(int mode, int pid) {
     case ENC_ARRAYS: return enc_ptr<ENC_ARRAYS>(pid);
     case ENC_STREAM: return enc_ptr<ENC_STREAM>(pid);
     case ENC_SAMPLE: return enc_ptr<ENC_SAMPLE>(pid);
+    case ENC_CODE: return enc_ptr<ENC_CODE>(pid);
     default: return enc_ptr<ENC_CHECK>(pid);
   }
 }

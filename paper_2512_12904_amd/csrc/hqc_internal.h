@@ -45,7 +45,7 @@ struct SetInfo {
   // per-item intermediates of a debug launch, at these byte offsets: the
   // received word v + u*y (n1*n2 bits, little-endian dwords), the RM
   // symbols (n1), the syndromes S_1..S_2delta, Lambda (2 delta + 1
-  // coefficients, times a nonzero constant), the error values at the k
+  // coefficients, Lambda_0 = 1), the error values at the k
   // message positions
   size_t dbg_bytes, dbg_sym, dbg_s, dbg_lam, dbg_e;
 };

@@ -13,8 +13,12 @@ namespace hqc {
 // 32-bit draws (ENC_STREAM, ENC_CHECK: Floyd's sampling, wr, wr, we draws);
 // ENC_CHECK compares the result with (u_in, v_in) instead of storing it and
 // writes ok[item] = 1 when every word is equal, else 0.  ENC_SAMPLE only
-// samples the supports from the draws and stores them.
-enum EncMode : int { ENC_KEYGEN = 0, ENC_ARRAYS = 1, ENC_STREAM = 2, ENC_CHECK = 3, ENC_SAMPLE = 4 };
+// samples the supports from the draws and stores them.  ENC_CODE only
+// encodes: v_out = the concatenated codeword of (the RS codeword of m) +
+// sym_err (count rows of n1 bytes; NULL: none).
+enum EncMode : int {
+  ENC_KEYGEN = 0, ENC_ARRAYS = 1, ENC_STREAM = 2, ENC_CHECK = 3, ENC_SAMPLE = 4, ENC_CODE = 5
+};
 struct EncArgs {
   const uint64_t *h, *s;
   const uint32_t *x, *y;
@@ -25,6 +29,7 @@ struct EncArgs {
   uint64_t *s_out, *u_out, *v_out;
   uint32_t *ok;                 // ENC_CHECK
   uint32_t *supp_out;           // ENC_SAMPLE: rows of 2 wr + we indices (r1, r2, e)
+  const uint8_t *sym_err;       // ENC_CODE: NULL or count rows of n1 bytes
   uint32_t draw_stride;
   uint32_t count;
 };

@@ -574,17 +574,18 @@ __device__ __forceinline__ void elem_masks(const uint32_t (&P)[8][NC], bool uppe
 
 // ---- S7: Berlekamp-Massey on bit-sliced vectors --------------------------------
 // Massey's recursion (Lambda <- Lambda + (Delta / b) x^s B, B <- Lambda and
-// b <- Delta when 2L <= r - 1) in the reformulated form of Sarwate and
-// Shanbhag (riBM): the discrepancies are not inner products but the low
-// part of a vector D that is updated like Lambda.  With D holding
+// b <- Delta when 2L <= r - 1) with the discrepancies read from a vector,
+// as in the reformulation of Sarwate and Shanbhag: they are not inner
+// products but the low part of a vector D that is updated like Lambda.
+// Massey's division by b (here gamma) is kept, so nothing is scaled.  With D holding
 // S_1 .. S_2delta in region A and Lambda in region C (coefficient q at
 // element q), step r is
 //     Delta = D_A[r],  c = Delta / gamma,
 //     U = swap ? D : T,  D <- D + c T,  T <- x U,
 //     gamma <- swap ? Delta : gamma,
 // swap = (Delta != 0 and 2L <= r), on both regions alike (T starts as x D).
-// Region C then holds Lambda times a nonzero constant (the same Lambda
-// sequence as Massey's form; roots and Omega / Lambda' are unchanged).
+// Region C then holds Massey's Lambda itself (Lambda_0 = 1, exactly the
+// oracle's coefficients, decoder failures included).
 // Elements of region A below r and of region C above 2 delta are never
 // read; they only move upwards, so they never reach the live elements.
 template <int NC>

@@ -28,9 +28,10 @@ F_GRAPH = 0x2
 EXPORTS = (
     "hqc_sizes", "hqc_decrypt_batch", "hqc_decode_batch", "hqc_decrypt_mixed",
     "hqc_decode_mixed", "hqc_keystore_create", "hqc_keystore_put", "hqc_keystore_put_many",
-    "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed", "hqc_strerror",
+    "hqc_keystore_destroy", "hqc_keystore_bad_ids", "hqc_decrypt_batch_keyed",
+    "hqc_decrypt_mixed_keyed", "hqc_strerror",
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
-    "hqc_encrypt_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
+    "hqc_encrypt_batch", "hqc_code_encode_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
     "hqc_kem_decaps_batch", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
     "hqc_ring_mul_batch", "hqc_autotune_decrypt", "hqc_tune_set", "hqc_tune_get",
     "hqc_tune_clear", "hqc_debug_bytes", "hqc_decrypt_debug",
@@ -94,12 +95,15 @@ def lib():
         L.hqc_keystore_destroy.argtypes = [vp]
         L.hqc_keystore_bad_ids.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.hqc_decrypt_batch_keyed.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, sz]
+        L.hqc_decrypt_mixed_keyed.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(Segment),
+                                              ctypes.c_int]
         L.hqc_strerror.restype = ctypes.c_char_p
         L.hqc_strerror.argtypes = [ctypes.c_int]
         L.hqc_last_hip_error.argtypes = []
         L.hqc_default_grid.argtypes = [ctypes.c_int]
         L.hqc_keygen_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, sz]
         L.hqc_encrypt_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp, sz]
+        L.hqc_code_encode_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, sz]
         L.hqc_kem_workspace_bytes.restype = ctypes.c_size_t
         L.hqc_kem_workspace_bytes.argtypes = [ctypes.c_int, sz]
         L.hqc_kem_encaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, sz,
@@ -199,7 +203,7 @@ def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None, tile=0):
     return out
 
 
-def _segments(items, decode):
+def _segments(items, decode, keyed=False):
     segs = (Segment * len(items))()
     outs = []
     for i, it in enumerate(items):
@@ -214,7 +218,10 @@ def _segments(items, decode):
         segs[i].u = _dev(u, torch.int64, "u/r", (count, s["v_words"] if decode else s["u_words"]))
         if not decode:
             segs[i].v = _dev(it["v"], torch.int64, "v", (count, s["v_words"]))
-            segs[i].y = _dev(it["y"], torch.int32, "y", (count, s["w"]))
+            if keyed:
+                segs[i].y = _dev(it["key_ids"], torch.int32, "key_ids", (count,))
+            else:
+                segs[i].y = _dev(it["y"], torch.int32, "y", (count, s["w"]))
         segs[i].m_out = _dev(out, torch.uint8, "out", (count, s["k"]))
     return segs, outs
 
@@ -292,6 +299,17 @@ def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, strea
     return out
 
 
+def decrypt_mixed_keyed(ks, items, flags=0, grid=0, stream=None, tile=0):
+    """One launch over several parameter sets with keys from the keystore.
+    items: list of dicts with pid, u, v, key_ids (int32 [count]) and
+    optionally out; returns the list of outputs."""
+    segs, outs = _segments(items, decode=False, keyed=True)
+    p = _params(0, flags, grid, stream, tile)
+    _check(lib().hqc_decrypt_mixed_keyed(ctypes.byref(p), ks.handle, segs, len(items)),
+           "hqc_decrypt_mixed_keyed")
+    return outs
+
+
 def keygen_batch(pid, h, x, y, out=None, grid=0, stream=None):
     """s[i] = x[i] + h[i]*y[i] (Alg. 3; the randomness h, x, y is an input)."""
     sz = sizes(pid)
@@ -328,6 +346,23 @@ def encrypt_batch(pid, h, s, m, r1, r2, e, u_out=None, v_out=None, grid=0, strea
         _dev(v_out, torch.int64, "v_out", (count, sz["v_words"])), count)
     _check(rc, "hqc_encrypt_batch")
     return u_out, v_out
+
+
+def code_encode_batch(pid, m, sym_err=None, out=None, grid=0, stream=None):
+    """r[i] = the concatenated codeword (Sec. II-A) of the RS codeword of m[i]
+    plus sym_err[i] (uint8 [count, n1], or None for C.Encode(m[i]))."""
+    sz = sizes(pid)
+    count = m.shape[0]
+    if out is None:
+        out = torch.empty((count, sz["v_words"]), dtype=torch.int64, device=m.device)
+    p = _params(pid, 0, grid, stream)
+    err = ctypes.c_void_p(0) if sym_err is None else _dev(sym_err, torch.uint8, "sym_err",
+                                                         (count, sz["n1"]))
+    rc = lib().hqc_code_encode_batch(ctypes.byref(p), _dev(m, torch.uint8, "m", (count, sz["k"])),
+                                     err, _dev(out, torch.int64, "out", (count, sz["v_words"])),
+                                     count)
+    _check(rc, "hqc_code_encode_batch")
+    return out
 
 
 def default_grid(pid):
@@ -490,7 +525,7 @@ def decrypt_debug(pid, u, v, y, flags=0, grid=0, stream=None, tile=0):
     """decrypt_batch plus each item's intermediates (hqc_decrypt_debug):
     returns (m, record) with record a dict of numpy arrays: "r" (received
     word, count x n1*n2/64 uint64), "sym" (RM symbols), "S" (syndromes),
-    "lam" (Lambda times a nonzero constant), "e" (error values at the
+    "lam" (the error locator Lambda, Lambda_0 = 1), "e" (error values at the
     message positions)."""
     sz = sizes(pid)
     count = u.shape[0]

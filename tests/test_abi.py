@@ -87,6 +87,9 @@ def test_invalid_arguments_rejected_before_launch(gpu_lib):
     assert L.hqc_keystore_create(None, None) == gpu_lib.HQC_EINVAL
     assert L.hqc_keystore_destroy(None) == gpu_lib.HQC_EINVAL
     assert L.hqc_decrypt_batch_keyed(ctypes.byref(p), None, vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
+    one = (gpu_lib.Segment * 1)()
+    one[0].param_id = 1
+    assert L.hqc_decrypt_mixed_keyed(ctypes.byref(p), None, one, 1) == gpu_lib.HQC_EINVAL
 
 
 def test_host_pointer_rejected_without_gpu(gpu_lib):

@@ -77,3 +77,28 @@ def test_gpu_round_trip(hqc, pid):
     got = hqc.decrypt_batch(pid, u, v, yd)
     torch.cuda.synchronize()
     assert torch.equal(got, dev(m))
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_code_encode_matches_oracle(hqc, pid):
+    """hqc_code_encode_batch: C.Encode(m) against the oracle's concatenated
+    encoder, and with a symbol-error pattern (delta symbols, the decoder
+    stress construction) plus the drawn noise against the oracle's stress
+    words; 200 items (a ragged tail at every grid) in two launch shapes."""
+    print("case: code encode pid=%d" % pid, flush=True)
+    p = datasets.sizes(pid)
+    cnt = 200
+    m, bad, dval, noise = synth.stress(0xE0C + pid, pid, p, cnt)
+    m[0] = 0
+    m[1] = 0xFF
+    ref = np.stack([oracle.code_encode(pid, mm) for mm in m])
+    for grid in (0, 3):
+        got = host(hqc.code_encode_batch(pid, dev(m), grid=grid)).view(np.uint64)
+        assert (got == ref).all(), grid
+    err = np.zeros((cnt, p["n1"]), np.uint8)
+    np.put_along_axis(err, bad.astype(np.int64), dval, axis=1)
+    r = host(hqc.code_encode_batch(pid, dev(m), sym_err=dev(err))).view(np.uint64) ^ noise
+    want = oracle.stress_batch(pid, m, bad, dval, noise)
+    assert (r == want).all()
+    # the stress words decode to m on the GPU
+    assert (host(hqc.decode_batch(pid, dev(r))) == m).all()

@@ -61,20 +61,8 @@ def test_ragged_counts_and_persistent_grid(hqc, pid, count, grid):
 
 @pytest.mark.parametrize("pid", [1, 3, 5])
 def test_beyond_radius_matches_oracle(hqc, pid):
-    # uniform u, v and arbitrary y (indices >= n, repeats, 0 and n-1): no valid
-    # message exists, the output is fixed only by the decoder conventions
     say("case: beyond radius pid=%d" % pid)
-    p = datasets.sizes(pid)
-    cnt = 96
-    u = synth.words(0x51 + pid, (cnt, p["nwords"]))
-    v = synth.words(0x61 + pid, (cnt, p["vwords"]))
-    rng = np.random.default_rng(pid)
-    y = rng.integers(0, 2 ** 32, (cnt, p["w"]), dtype=np.uint64).astype(np.uint32)
-    y[0, :] = 0
-    y[1, :2] = [0, p["n"] - 1]
-    y[2, :] = p["n"] - 1
-    y[3, 1] = y[3, 0]
-    y[4:40] %= p["n"]
+    u, v, y = _random_inputs(pid)
     got = host(hqc.decrypt_batch(pid, dev(u), dev(v), dev(y)))
     ref = oracle.decrypt_batch(pid, y, u, v)
     assert (got == ref).all()
@@ -205,14 +193,12 @@ def _words(bits):
     return np.packbits(bits, bitorder="little").view(np.uint64)
 
 
-@pytest.mark.parametrize("pid", [1, 3, 5])
-def test_structured_beyond_radius_matches_oracle(hqc, pid):
-    """Words built to sit at the decoders' edges, decoded by the GPU and the
-    oracle: codewords with exactly delta + 1, delta + 2 and 2 delta wrong RS
-    symbols (just past the radius: Berlekamp-Massey ends above degree delta),
-    blocks set to all zeros or all ones, and blocks equidistant from two RM
-    codewords (Hadamard peaks of equal magnitude: the tie rule decides)."""
-    say("case: structured beyond radius pid=%d" % pid)
+def _structured_words(pid):
+    """Received words at the decoders' edges: codewords with exactly
+    delta + 1, delta + 2 and 2 delta wrong RS symbols (just past the radius:
+    Berlekamp-Massey ends above degree delta), blocks set to all zeros or all
+    ones, and blocks equidistant from two RM codewords (Hadamard peaks of
+    equal magnitude: the tie rule decides).  64 words, 8 of each kind."""
     p = datasets.sizes(pid)
     par = oracle.param(pid)
     n1, n2, delta = par["n1"], par["n2"], par["delta"]
@@ -252,10 +238,130 @@ def test_structured_beyond_radius_matches_oracle(hqc, pid):
                     c[flip] ^= 1
                     blocks[blk] = _words(c)
             rows.append(r)
-    r = np.stack(rows)
+    return np.stack(rows)
+
+
+def _random_inputs(pid, cnt=96):
+    """Uniform u and v with arbitrary y (indices >= n, repeats, 0 and n - 1):
+    no valid message exists, the output is fixed only by the decoder
+    conventions."""
+    p = datasets.sizes(pid)
+    u = synth.words(0x51 + pid, (cnt, p["nwords"]))
+    v = synth.words(0x61 + pid, (cnt, p["vwords"]))
+    rng = np.random.default_rng(pid)
+    y = rng.integers(0, 2 ** 32, (cnt, p["w"]), dtype=np.uint64).astype(np.uint32)
+    y[0, :] = 0
+    y[1, :2] = [0, p["n"] - 1]
+    y[2, :] = p["n"] - 1
+    y[3, 1] = y[3, 0]
+    y[4:40] %= p["n"]
+    return u, v, y
+
+
+@pytest.mark.parametrize("pid", [1, 3, 5])
+def test_structured_beyond_radius_matches_oracle(hqc, pid):
+    """_structured_words decoded by the GPU and the oracle, then decrypted
+    with u = 0."""
+    say("case: structured beyond radius pid=%d" % pid)
+    p = datasets.sizes(pid)
+    r = _structured_words(pid)
     got = host(hqc.decode_batch(pid, dev(r)))
     assert (got == oracle.decode_batch(pid, r)).all()
     # the same words through decryption with u = 0
-    z = np.zeros((len(rows), p["nwords"]), np.uint64)
-    y = np.tile(np.arange(p["w"], dtype=np.uint32), (len(rows), 1))
+    z = np.zeros((len(r), p["nwords"]), np.uint64)
+    y = np.tile(np.arange(p["w"], dtype=np.uint32), (len(r), 1))
     assert (host(hqc.decrypt_batch(pid, dev(z), dev(r), dev(y))) == got).all()
+
+
+@pytest.mark.parametrize("tile", [0, 64])
+def test_mixed_kernel_beyond_radius_matches_oracle(hqc, tile):
+    """The three-set kernel (the instance the decoder-stress launch runs) on
+    the inputs of the single-set beyond-radius tests: random ciphertexts with
+    arbitrary keys, uniformly random received words and the structured edge
+    words, all three sets in one launch each, every byte against the oracle.
+    Tile 0 is the library's choice (lane pairs at these sizes), 64 the
+    one-lane Reed-Solomon form for HQC-1 and HQC-3."""
+    say("case: mixed kernel beyond radius tile=%d" % tile)
+    sets = (1, 3, 5)
+    rnd = {pid: _random_inputs(pid) for pid in sets}
+    outs = hqc.decrypt_mixed([{"pid": pid, "u": dev(u), "v": dev(v), "y": dev(y)}
+                              for pid, (u, v, y) in rnd.items()], grid=11, tile=tile)
+    for (pid, (u, v, y)), o in zip(rnd.items(), outs):
+        assert (host(o) == oracle.decrypt_batch(pid, y, u, v)).all(), pid
+    words = {}
+    for pid in sets:
+        p = datasets.sizes(pid)
+        rw = synth.words(0x81 + pid, (32, p["vwords"]))
+        rw[0] = 0
+        rw[1] = np.uint64(0xFFFFFFFFFFFFFFFF)
+        words[pid] = np.concatenate([_structured_words(pid), rw])
+    outs = hqc.decode_mixed([{"pid": pid, "r": dev(r)} for pid, r in words.items()],
+                            grid=5, tile=tile)
+    for (pid, r), o in zip(words.items(), outs):
+        assert (host(o) == oracle.decode_batch(pid, r)).all(), pid
+    # the same words through the mixed decryption with u = 0
+    items = []
+    for pid, r in words.items():
+        p = datasets.sizes(pid)
+        z = np.zeros((len(r), p["nwords"]), np.uint64)
+        y = np.tile(np.arange(p["w"], dtype=np.uint32), (len(r), 1))
+        items.append({"pid": pid, "u": dev(z), "v": dev(r), "y": dev(y)})
+    outs2 = hqc.decrypt_mixed(items, tile=tile)
+    for o, o2 in zip(outs, outs2):
+        assert (host(o) == host(o2)).all()
+
+
+@pytest.mark.parametrize("tile", [0, 64])
+def test_keyed_kernels_beyond_radius_match_oracle(hqc, tile):
+    """The keyed kernel (the instance the serving loop runs), per set and as
+    one mixed launch, on random ciphertexts and on the structured edge words
+    (u = 0), with keystore keys that include the extreme supports
+    {0 .. w-1} and {n-w .. n-1}; every byte against the oracle."""
+    import torch
+    say("case: keyed kernels beyond radius tile=%d" % tile)
+    sets = (1, 3, 5)
+    nkeys = 8
+    keys, cases = {}, {}
+    for pid in sets:
+        p = datasets.sizes(pid)
+        y = synth.keys(0x91 + pid, pid, p, nkeys)[2]
+        y[0] = np.arange(p["w"], dtype=np.uint32)
+        y[1] = np.arange(p["n"] - p["w"], p["n"], dtype=np.uint32)
+        keys[pid] = y
+    ks = hqc.KeyStore(nkeys, nkeys, nkeys)
+    try:
+        for pid in sets:
+            ks.put(pid, 0, keys[pid])
+        for pid in sets:
+            p = datasets.sizes(pid)
+            cnt = 80
+            u = synth.words(0xA1 + pid, (cnt, p["nwords"]))
+            v = synth.words(0xA2 + pid, (cnt, p["vwords"]))
+            r = _structured_words(pid)
+            u = np.concatenate([u, np.zeros((len(r), p["nwords"]), np.uint64)])
+            v = np.concatenate([v, r])
+            kid = (np.arange(len(u)) * 5 % nkeys).astype(np.uint32)
+            cases[pid] = (u, v, kid, oracle.decrypt_batch(pid, keys[pid][kid], u, v))
+        for pid, (u, v, kid, ref) in cases.items():
+            got = host(hqc.decrypt_batch_keyed(pid, ks, dev(u), dev(v), dev(kid), tile=tile))
+            assert (got == ref).all(), pid
+        outs = hqc.decrypt_mixed_keyed(ks, [{"pid": pid, "u": dev(u), "v": dev(v), "key_ids": dev(kid)}
+                                            for pid, (u, v, kid, _) in cases.items()],
+                                       grid=7, tile=tile)
+        for (pid, (u, v, kid, ref)), o in zip(cases.items(), outs):
+            assert (host(o) == ref).all(), pid
+        assert ks.bad_ids() == 0
+        # an out-of-range id in one segment of a mixed launch: zeros there, counted
+        u, v, kid, ref = cases[3]
+        kid = kid.copy()
+        kid[4] = nkeys + 100
+        outs = hqc.decrypt_mixed_keyed(ks, [{"pid": 3, "u": dev(u), "v": dev(v), "key_ids": dev(kid)},
+                                            {"pid": 1, "u": dev(cases[1][0]), "v": dev(cases[1][1]),
+                                             "key_ids": dev(cases[1][2])}], tile=tile)
+        got3 = host(outs[0])
+        assert (got3[4] == 0).all() and (np.delete(got3, 4, 0) == np.delete(ref, 4, 0)).all()
+        assert (host(outs[1]) == cases[1][3]).all()
+        assert ks.bad_ids() == 1
+        torch.cuda.synchronize()
+    finally:
+        ks.close()
