@@ -314,60 +314,110 @@ def pct(xs, q):
     return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
 
 
-def decode_stress_bench(hqc, device, total=1 << 20, reps=5, chunk=65536):
-    """The decoder stress workload: total received words, 50/30/20 % HQC-1/3/5,
-    decoded by one mixed hipGraph launch (hqc_decode_mixed).  The words are
-    made on the device by the library's encryption with h = s = 0, so v = mG
-    + e: codewords of seeded messages plus a weight-we error (the kernel's
-    time does not depend on the data).  Device time per launch from HIP
-    events over reps launches after one untimed one; every message checked."""
+def stress_words(hqc, pid, count, seed, device, chunk=65536):
+    """count decoder-stress words of one set, made on the device: per word the
+    seeded draws (m, delta distinct blocks with nonzero symbol errors, noise
+    of U{0..rho} flips at distinct positions in every other block; host
+    draws, no arithmetic) go through the library's encoder
+    (hqc_code_encode_batch: RS codeword of m plus the symbol errors, each
+    symbol a duplicated RM block), then the noise is XORed in.  Exactly
+    delta RS symbols are wrong and every other block is within the RM
+    radius, so each word decodes to m.  Returns (r, m) on the device."""
     import numpy as np
     import torch
     from paper_2512_12904_amd import synth
-    counts = {1: total // 2, 3: total * 3 // 10}
-    counts[5] = total - counts[1] - counts[3]
-    items, msgs = [], []
-    for pid, c in counts.items():
-        s = dict(SETS[pid])
-        U = (s["n"] + 63) // 64
-        zero = torch.zeros((min(chunk, c), U), dtype=torch.int64, device=device)
-        r = torch.empty((c, s["n1"] * s["n2"] // 64), dtype=torch.int64, device=device)
-        m_all = torch.empty((c, s["k"]), dtype=torch.uint8, device=device)
-        for a in range(0, c, chunk):
-            b = min(c, a + chunk)
-            m, r1, r2, e = synth.encryptions(0x4E00 + pid, pid, s, b - a, ct_id0=a)
-            t = lambda x, dt: torch.from_numpy(x.view(dt) if x.dtype != np.uint8 else x).to(device)
-            md = t(m, np.uint8)
-            hqc.encrypt_batch(pid, zero[:b - a], zero[:b - a], md, t(r1, np.int32), t(r2, np.int32),
-                              t(e, np.int32), v_out=r[a:b])
-            m_all[a:b] = md
-        items.append({"pid": pid, "r": r})
-        msgs.append(m_all)
-    torch.cuda.synchronize()
+    s = dict(SETS[pid])
+    s["rho"] = (64 * (s["n2"] // 128) - 1) // 2  # RM unique radius: 95 / 159
+    r = torch.empty((count, s["n1"] * s["n2"] // 64), dtype=torch.int64, device=device)
+    m_all = torch.empty((count, s["k"]), dtype=torch.uint8, device=device)
+    for a in range(0, count, chunk):
+        b = min(count, a + chunk)
+        m, bad, dval, noise = synth.stress(seed, pid, s, b - a, word_id0=a)
+        err = np.zeros((b - a, s["n1"]), np.uint8)
+        np.put_along_axis(err, bad.astype(np.int64), dval, axis=1)
+        md = torch.from_numpy(m).to(device)
+        hqc.code_encode_batch(pid, md, sym_err=torch.from_numpy(err).to(device), out=r[a:b])
+        r[a:b] ^= torch.from_numpy(noise.view(np.int64)).to(device)
+        m_all[a:b] = md
+    return r, m_all
+
+
+def mg_plus_e_words(hqc, pid, count, seed, device, chunk=65536):
+    """count words v = mG + e (the library's encryption with h = s = 0: the
+    codeword of a seeded m plus a weight-we error over the first n1*n2
+    bits).  Returns (r, m) on the device."""
+    import numpy as np
+    import torch
+    from paper_2512_12904_amd import synth
+    s = dict(SETS[pid])
+    U = (s["n"] + 63) // 64
+    zero = torch.zeros((min(chunk, count), U), dtype=torch.int64, device=device)
+    r = torch.empty((count, s["n1"] * s["n2"] // 64), dtype=torch.int64, device=device)
+    m_all = torch.empty((count, s["k"]), dtype=torch.uint8, device=device)
+    t = lambda x, dt: torch.from_numpy(x.view(dt) if x.dtype != np.uint8 else x).to(device)
+    for a in range(0, count, chunk):
+        b = min(count, a + chunk)
+        m, r1, r2, e = synth.encryptions(seed, pid, s, b - a, ct_id0=a)
+        md = t(m, np.uint8)
+        hqc.encrypt_batch(pid, zero[:b - a], zero[:b - a], md, t(r1, np.int32), t(r2, np.int32),
+                          t(e, np.int32), v_out=r[a:b])
+        m_all[a:b] = md
+    return r, m_all
+
+
+def time_decode_mixed(hqc, items, msgs, reps):
+    """Device time per launch of one mixed hipGraph launch of
+    hqc_decode_mixed over items (HIP events on the launch stream, reps
+    launches after one untimed one, median) and whether every message
+    equals msgs."""
+    import torch
     stream = torch.cuda.current_stream()
     outs = hqc.decode_mixed(items, flags=hqc.F_GRAPH, stream=stream)
     torch.cuda.synchronize()
     ok = all(bool(torch.equal(o, m)) for o, m in zip(outs, msgs))
+    for it, o in zip(items, outs):
+        it["out"] = o
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record(stream)
     for i in range(reps):
-        for it, o in zip(items, outs):
-            it["out"] = o
         hqc.decode_mixed(items, flags=hqc.F_GRAPH, stream=stream)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     times = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-    ms = sorted(times)[len(times) // 2]
-    ops = sum(decode_op_model(pid) * c for pid, c in counts.items())
-    r = {"words": total, "mix": {"HQC-%d" % p: c for p, c in counts.items()},
-         "ms_median": ms, "words_per_s": total / (ms / 1e3),
-         # can exceed 1: the model counts one op per received bit and per
-         # butterfly, and the RM stage (most of decoding) does two butterflies
-         # per packed 16-bit instruction
-         "op_model_frac": ops / (ms / 1e3) / PEAK_INT_OPS, "all_messages_recovered": ok}
-    del items, outs, msgs
-    torch.cuda.empty_cache()
-    return r
+    # the messages of the last timed launch too
+    ok = ok and all(bool(torch.equal(o, m)) for o, m in zip(outs, msgs))
+    return sorted(times)[len(times) // 2], times, ok
+
+
+def decode_stress_bench(hqc, device, total=1 << 20, reps=5):
+    """The decoder stress workload: total received words, 50/30/20 % HQC-1/3/5,
+    decoded by one mixed hipGraph launch (hqc_decode_mixed) -- on the stress
+    words (exactly delta wrong RS symbols through whole RM blocks, noise
+    within the RM radius elsewhere; stress_words), and, beside it, on words
+    v = mG + e (mg_plus_e_words).  Every message is checked."""
+    import torch
+    counts = {1: total // 2, 3: total * 3 // 10}
+    counts[5] = total - counts[1] - counts[3]
+    out = {"words": total, "mix": {"HQC-%d" % p: c for p, c in counts.items()}}
+    for name, make in (("stress", stress_words), ("mg_plus_e", mg_plus_e_words)):
+        t0 = time.perf_counter()
+        data = {pid: make(hqc, pid, c, 0x4E00 + pid, device) for pid, c in counts.items()}
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t0
+        items = [{"pid": pid, "r": r} for pid, (r, _) in data.items()]
+        ms, times, ok = time_decode_mixed(hqc, items, [m for _, m in data.values()], reps)
+        res = {"ms_median": ms, "ms_all": [round(t, 4) for t in times],
+               "words_per_s": total / (ms / 1e3), "all_messages_recovered": ok,
+               "generation_s": round(gen_s, 2)}
+        if name == "stress":
+            res["words"] = "exactly delta RS symbol errors via whole RM blocks + U{0..rho} flips elsewhere"
+            out.update(res)
+        else:
+            res["words"] = "mG + e, e of weight we"
+            out["mg_plus_e"] = res
+        del data, items
+        torch.cuda.empty_cache()
+    return out
 
 
 def gpu_info(device):
@@ -412,7 +462,10 @@ def cpu_baseline(seconds_target=12.0):
     from paper_2512_12904_amd import synth
     pid = 1
     p = oracle.param(pid)
-    threads = oracle.default_threads()
+    # every CPU this process may run on, up to 16: one GPU's share of the host
+    # cores on the machines this runs on, whatever more the affinity mask shows
+    affinity = len(os.sched_getaffinity(0))
+    threads = min(affinity, 16)
     # calibrate on a small batch, then size each run to a third of the target
     cnt0 = 512
     h, x, y = synth.keys(0xC0, pid, p, cnt0)
@@ -444,6 +497,7 @@ def cpu_baseline(seconds_target=12.0):
     single = 64 * reps1 / (time.perf_counter() - t0)
     ok = ok and bool((got1 == m[:64]).all())
     return {"value": sorted(rates)[1], "unit": "decrypts/s", "cores": threads, "kind": "oracle",
+            "affinity_cpus": affinity, "os_cpu_count": os.cpu_count(),
             "runs": rates, "single_core_value": single, "cpu_model": cpu_model(),
             "sample": "median of 3 runs of %d decryptions (%d HQC-1 ciphertexts x %d passes), honest "
                       "ciphertexts from the checker, %d threads, %.1f s in all; single thread: "
@@ -451,43 +505,86 @@ def cpu_baseline(seconds_target=12.0):
             "recovered_m": ok}, (pid, y, u, v, m)
 
 
-def serving_bench(device, loads, seconds, streams=4, budget=1 << 30):
-    """Poisson arrivals of decryption requests (parameter set 50/30/20 %,
-    b uniform in 1..4096 ciphertexts under one key, 10,000 device-resident
-    keys split 5,000 / 3,000 / 2,000) at each offered load in decrypts/s;
-    latency from arrival to the messages on the host."""
+def serving_pools(hqc, counts, per_key, device, seed=0x5E00):
+    """Per-key pools of honest ciphertexts for the serving loop: for each set,
+    counts[pid] keys (seeded draws through the library's key generation)
+    and per_key ciphertexts under each key (seeded draws through the
+    library's encryption), laid out key-major in pinned host memory: u, v,
+    the key id of every row, and the drawn messages (numpy) for checking.
+    Returns (pools, y) with y[pid] the keys' supports (host)."""
     import numpy as np
     import torch
-    from paper_2512_12904_amd import hqc, serve, synth
-    counts = {1: 5000, 3: 3000, 5: 2000}
-    ks = hqc.KeyStore(counts[1], counts[3], counts[5])
-    pools, rows = {}, {}
-    for pid in (1, 3, 5):
+    from paper_2512_12904_amd import synth
+    pools, ys = {}, {}
+    for pid, nk in counts.items():
         s = dict(SETS[pid])
-        _, _, y = synth.keys(0x5E00 + pid, pid, s, counts[pid])
-        ks.put(pid, 0, y)
-        rows[pid] = 8192
-        u = synth.words(0x5E10 + pid, (rows[pid], (s["n"] + 63) // 64))
-        v = synth.words(0x5E20 + pid, (rows[pid], s["n1"] * s["n2"] // 64))
-        pools[pid] = (torch.from_numpy(u.view(np.int64)).pin_memory(),
-                      torch.from_numpy(v.view(np.int64)).pin_memory())
+        h, x, y = synth.keys(seed + pid, pid, s, nk)
+        key_of = np.repeat(np.arange(nk, dtype=np.int64), per_key)
+        m, r1, r2, e = synth.encryptions(seed + 0x10 + pid, pid, s, len(key_of), key_of=key_of)
+        t = lambda a, dt: torch.from_numpy(a.view(dt) if a.dtype != np.uint8 else a).to(device)
+        hd = t(h, np.int64)
+        sd = hqc.keygen_batch(pid, hd, t(x, np.int32), t(y, np.int32))
+        kd = torch.from_numpy(key_of).to(device)
+        u, v = hqc.encrypt_batch(pid, hd.index_select(0, kd), sd.index_select(0, kd), t(m, np.uint8),
+                                 t(r1, np.int32), t(r2, np.int32), t(e, np.int32))
+        torch.cuda.synchronize()
+        pools[pid] = {"u": u.cpu().pin_memory(), "v": v.cpu().pin_memory(),
+                      "key": torch.from_numpy(key_of.astype(np.int32)).pin_memory(), "m": m}
+        ys[pid] = y
+        del hd, sd, kd, u, v
+    torch.cuda.empty_cache()
+    return pools, ys
+
+
+def serving_bench(device, loads, seconds, streams=4, budget=1 << 30, per_key=16):
+    """Poisson arrivals of decryption requests (parameter set 50/30/20 %,
+    b uniform in 1..4096 ciphertexts, 10,000 device-resident keys split
+    5,000 / 3,000 / 2,000) at each offered load in decrypts/s, for `seconds`
+    each; a request's ciphertexts are a run of consecutive rows of its set's
+    key-major pool of honest ciphertexts (per_key per key), each row with
+    its key id; latency from arrival to the messages on the host; every
+    served message checked against the encrypted one."""
+    import torch
+    from paper_2512_12904_amd import hqc, serve
+    counts = {1: 5000, 3: 3000, 5: 2000}
+    t0 = time.perf_counter()
+    pools, ys = serving_pools(hqc, counts, per_key, device)
+    gen_s = time.perf_counter() - t0
+    ks = hqc.KeyStore(counts[1], counts[3], counts[5])
+    for pid in (1, 3, 5):
+        ks.put(pid, 0, ys[pid])
+    rows = {pid: counts[pid] * per_key for pid in counts}
     srv = serve.Server(ks, pools, streams=streams, budget_bytes=budget, device=device)
-    # warm the slots (graph-free launches, allocator, copies)
+    # warm the slots (allocator, copies, kernels)
     srv.run(serve.poisson_requests(2e6, 0.05, counts, 1, pool_rows=rows), realtime=False)
-    out = {}
+    out = {"pool": "%d keys x %d honest ciphertexts per key (%.2f GB pinned host), made in %.1f s"
+                   % (sum(counts.values()), per_key,
+                      sum(p["u"].nbytes + p["v"].nbytes for p in pools.values()) / 1e9, gen_s),
+           "seconds_per_load": seconds, "streams": streams, "budget_bytes": budget}
     for load in loads:
         reqs = serve.poisson_requests(load, seconds, counts, int(load) & 0xFFFF, pool_rows=rows)
+        srv.checked = srv.mismatches = srv.launches = 0
         wall = srv.run(reqs)
         st = serve.latency_stats(reqs, wall)
         st["offered_decrypts_per_s"] = load
+        st["launches"] = srv.launches
+        st["messages_checked"] = srv.checked
+        st["all_messages_recovered"] = srv.checked == st["decrypts"] and srv.mismatches == 0
         out["%.0e" % load] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
     ks.close()
+    del pools, srv
+    torch.cuda.empty_cache()
     return out
 
 
 def main_checks(results):
     return all(r.get("all_messages_recovered", False) and r.get("kem_all_keys_match", True)
                and r.get("end_to_end_messages_recovered", True) for r in results.values())
+
+
+def serving_checks(serving):
+    return all(v.get("all_messages_recovered", False) for k, v in serving.items()
+               if isinstance(v, dict) and "offered_decrypts_per_s" in v)
 
 
 def main():
@@ -512,7 +609,7 @@ def main():
                          "then REPS of a random class (for counter comparison) and exit")
     ap.add_argument("--no-kem", action="store_true",
                     help="skip the KEM encapsulation / decapsulation timing")
-    ap.add_argument("--serving-seconds", type=float, default=2.0)
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--tile", type=int, default=0, help="items per workgroup (0 = library)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups (0 = library)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -639,6 +736,8 @@ def main():
     if not args.no_serving:
         line["serving"] = serving_bench(dev, (1e5, 1e6, 1e7), args.serving_seconds)
         line["p99_latency_ms_serving_1e6"] = line["serving"]["1e+06"]["p99_ms"]
+        if not serving_checks(line["serving"]):
+            print("serving: served messages differ from the encrypted ones", file=sys.stderr)
     if not args.no_cpu:
         cb, sample = cpu_baseline()
         # same run: the GPU decrypts the checker's sample and must agree bitwise

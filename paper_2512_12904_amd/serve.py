@@ -1,15 +1,17 @@
 """Continuous-batching decryption server on one GPU.
 
-Requests (parameter set, key id, b ciphertexts) arrive over time.  The
-server keeps the secret keys device-resident (a KeyStore), and runs S slots,
-each a HIP stream with its own device buffers of `budget / S` bytes.  While
-earlier batches are on the GPU, newly arrived requests are admitted into
-any free slot, as many as fit in its bytes (u + v + m of every item); a
-request larger than a slot is split across batches.  A slot's batch is one
-keyed decryption launch per parameter set present, with the ciphertexts
-copied host-to-device on the slot's stream and the messages copied back;
-a request is complete when all of its items are back on the host.  Latency
-is measured from the request's arrival time to that point.
+Requests (parameter set, b ciphertexts, each with its key id) arrive over
+time.  The server keeps the secret keys device-resident (a KeyStore), and
+runs S slots, each a HIP stream with its own device buffers of `budget / S`
+bytes.  While earlier batches are on the GPU, newly arrived requests are
+admitted into any free slot, as many as fit in its bytes (u + v + m + key id
+of every item); a request larger than a slot is split across batches.  A
+slot's batch is one keyed decryption launch over every parameter set present
+(hqc_decrypt_mixed_keyed), with the ciphertexts and key ids copied
+host-to-device on the slot's stream and the messages copied back; a request
+is complete when all of its items are back on the host.  Latency is
+measured from the request's arrival time to that point.  When the pools
+carry the expected messages, every served message is compared with them.
 
 Everything numeric runs in libhqc_gpu.so; this module schedules copies and
 launches (PyTorch supplies pinned memory, device memory and streams).
@@ -52,8 +54,6 @@ class _Slot:
         self.m = {pid: torch.empty((self.cap[pid], s["k"]), dtype=torch.uint8, device=device)
                   for pid, s in sizes.items()}
         self.kid = {pid: torch.empty(self.cap[pid], dtype=torch.int32, device=device) for pid in sizes}
-        self.kid_host = {pid: torch.empty(self.cap[pid], dtype=torch.int32, pin_memory=True)
-                         for pid in sizes}
         self.m_host = {pid: torch.empty((self.cap[pid], s["k"]), dtype=torch.uint8, pin_memory=True)
                        for pid, s in sizes.items()}
         self.fill = {pid: 0 for pid in sizes}
@@ -63,8 +63,12 @@ class _Slot:
 
 
 class Server:
-    """pools[pid] = (u_host, v_host): pinned int64 tensors holding the
-    ciphertexts requests refer to (request src = first row, rows src..src+b-1)."""
+    """pools[pid] = dict(u=..., v=..., key=..., m=...): pinned host tensors
+    u (int64 [rows, u_words]), v (int64 [rows, v_words]) and key (int32
+    [rows], the key id of each ciphertext) that requests refer to (request
+    src = first row, rows src .. src+b-1), and optionally m (numpy uint8
+    [rows, k]), the message of each row, against which every served message
+    is checked (counted in `mismatches`)."""
 
     def __init__(self, keystore, pools, streams=4, budget_bytes=512 << 20, device="cuda:0",
                  tile=0):
@@ -74,6 +78,9 @@ class Server:
         self.sizes = {pid: hqc.sizes(pid) for pid in SETS}
         self.slots = [_Slot(self.device, budget_bytes // streams, self.sizes) for _ in range(streams)]
         self.tile = tile
+        self.launches = 0
+        self.checked = 0
+        self.mismatches = 0
 
     # -- one batch --------------------------------------------------------
     def _launch(self, slot, queue):
@@ -89,11 +96,11 @@ class Server:
                     break
                 cnt = min(room, req.b - first)
                 off = slot.fill[pid]
-                u_host, v_host = self.pools[pid]
+                pool = self.pools[pid]
                 src = req.src + first
-                slot.u[pid][off:off + cnt].copy_(u_host[src:src + cnt], non_blocking=True)
-                slot.v[pid][off:off + cnt].copy_(v_host[src:src + cnt], non_blocking=True)
-                slot.kid_host[pid][off:off + cnt] = req.key
+                slot.u[pid][off:off + cnt].copy_(pool["u"][src:src + cnt], non_blocking=True)
+                slot.v[pid][off:off + cnt].copy_(pool["v"][src:src + cnt], non_blocking=True)
+                slot.kid[pid][off:off + cnt].copy_(pool["key"][src:src + cnt], non_blocking=True)
                 slot.parts.append((req, first, cnt, pid, off))
                 slot.fill[pid] += cnt
                 if first + cnt == req.b:
@@ -101,15 +108,16 @@ class Server:
                 else:
                     queue[0] = (req, first + cnt)
                     break  # this slot is full for that set
+            items = [{"pid": pid, "u": slot.u[pid][:slot.fill[pid]],
+                      "v": slot.v[pid][:slot.fill[pid]], "key_ids": slot.kid[pid][:slot.fill[pid]],
+                      "out": slot.m[pid][:slot.fill[pid]]} for pid in SETS if slot.fill[pid]]
+            # one launch for the whole batch, whatever sets it holds
+            hqc.decrypt_mixed_keyed(self.ks, items, stream=slot.stream, tile=self.tile)
+            self.launches += 1
             for pid in SETS:
                 f = slot.fill[pid]
-                if f == 0:
-                    continue
-                slot.kid[pid][:f].copy_(slot.kid_host[pid][:f], non_blocking=True)
-                hqc.decrypt_batch_keyed(pid, self.ks, slot.u[pid][:f], slot.v[pid][:f],
-                                        slot.kid[pid][:f], out=slot.m[pid][:f],
-                                        stream=slot.stream, tile=self.tile)
-                slot.m_host[pid][:f].copy_(slot.m[pid][:f], non_blocking=True)
+                if f:
+                    slot.m_host[pid][:f].copy_(slot.m[pid][:f], non_blocking=True)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
 
@@ -118,6 +126,12 @@ class Server:
         number of requests that became complete."""
         finished = 0
         for req, first, cnt, pid, off in slot.parts:
+            want = self.pools[pid].get("m")
+            if want is not None:
+                got = slot.m_host[pid][off:off + cnt].numpy()
+                src = req.src + first
+                self.mismatches += int(np.count_nonzero((got != want[src:src + cnt]).any(axis=1)))
+                self.checked += cnt
             if keep_results:
                 if req.m is None:
                     req.m = np.empty((req.b, self.sizes[pid]["k"]), np.uint8)
@@ -166,9 +180,10 @@ class Server:
 def poisson_requests(rate_decrypts, seconds, counts, seed, b_max=4096, mix=(0.5, 0.3, 0.2),
                      pool_rows=None):
     """Arrivals at `rate_decrypts` offered decryptions per second (requests
-    per second = rate / E[b]), parameter set drawn with `mix`, key uniform in
-    the set's keys, b uniform in 1..b_max, ciphertext rows uniform in the
-    set's pool."""
+    per second = rate / E[b]), parameter set drawn with `mix`, b uniform in
+    1..b_max, the first ciphertext row uniform in the set's pool (the rows
+    carry their own key ids; `key` records a uniform key id for the
+    record only)."""
     rng = np.random.default_rng(seed)
     mean_b = (1 + b_max) / 2.0
     lam = rate_decrypts / mean_b

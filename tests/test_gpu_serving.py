@@ -1,6 +1,8 @@
 """Serving loop: every request's messages are the same when served alone and
 inside the continuous-batching mix (integer work: tolerance zero), also when
-the memory budget forces requests to be split across batches."""
+the memory budget forces requests to be split across batches; each batch is
+one keyed launch over every parameter set it holds, and the server's own
+check of every served message against the pool's messages agrees."""
 import numpy as np
 import pytest
 
@@ -30,8 +32,10 @@ def env():
         m, r1, r2, e = synth.encryptions(0x77, pid, p, len(key_of), key_of=key_of)
         u, v = oracle.encrypt_batch(pid, h, s, m, r1, r2, e, key_of=key_of)
         ks.put(pid, 0, y)
-        pools[pid] = (torch.from_numpy(u.view(np.int64)).pin_memory(),
-                      torch.from_numpy(v.view(np.int64)).pin_memory())
+        pools[pid] = {"u": torch.from_numpy(u.view(np.int64)).pin_memory(),
+                      "v": torch.from_numpy(v.view(np.int64)).pin_memory(),
+                      "key": torch.from_numpy(key_of.astype(np.int32)).pin_memory(),
+                      "m": m}
         truth[pid] = m
     return hqc, ks, pools, truth, nkeys, per_key
 
@@ -58,14 +62,16 @@ def test_alone_equals_mixed(env, budget, streams, realtime):
     reqs = make_requests(nkeys, per_key, 60, 5, 2e-4 if realtime else 0.0)
     srv = Server(ks, pools, streams=streams, budget_bytes=budget)
     srv.run(reqs, keep_results=True, realtime=realtime)
+    assert srv.checked == sum(r.b for r in reqs) and srv.mismatches == 0
     for r in reqs:
         want = truth[r.pid][r.src:r.src + r.b]
         assert r.t_done is not None and r.t_done >= r.arrival
         assert (r.m == want).all(), r.rid
         # the same request alone, one keyed launch
-        u, v = pools[r.pid]
+        pool = pools[r.pid]
         kid = torch.full((r.b,), r.key, dtype=torch.int32, device="cuda")
-        alone = hqc.decrypt_batch_keyed(r.pid, ks, u[r.src:r.src + r.b].cuda(),
-                                        v[r.src:r.src + r.b].cuda(), kid)
+        assert (pool["key"][r.src:r.src + r.b] == r.key).all()
+        alone = hqc.decrypt_batch_keyed(r.pid, ks, pool["u"][r.src:r.src + r.b].cuda(),
+                                        pool["v"][r.src:r.src + r.b].cuda(), kid)
         torch.cuda.synchronize()
         assert (alone.cpu().numpy() == r.m).all()
