@@ -271,7 +271,7 @@ TILE = 0
 # the sources the decryption kernel is compiled from
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12904_amd", "csrc", f)
                   for f in ("hqc_kernels.hip", "hqc_device.h", "hqc_internal.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hqc1_b65536.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "decrypt_counters.json")
 
 
 def kernel_sha():
@@ -282,18 +282,20 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
-    WRITE_SIZE, scaled by the copy-kernel calibration), if they were taken on
-    the kernel source as it is now; else None."""
+def committed_counters(name):
+    """The committed rocprofv3 counter summary of one decryption kernel
+    (name: "HQC-1", "HQC-3", "HQC-5" at 65,536 items, or "decode_mixed" at
+    1,048,576 words): VALU busy, instructions per item and HBM bytes per
+    launch (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's counts) --
+    if they were taken on the kernel source as it is now; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256") != kernel_sha():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("kernels", {}).get(name)
 
 
 def copy_calibration(mib, device):
@@ -307,6 +309,11 @@ def copy_calibration(mib, device):
         dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def progress(msg):
+    """One line per finished bench stage, on stderr (the JSON line goes to stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
 def pct(xs, q):
@@ -536,6 +543,25 @@ def serving_pools(hqc, counts, per_key, device, seed=0x5E00):
     return pools, ys
 
 
+def host_link_GBps(device, mib=1024, reps=5):
+    """Pinned host-to-device copy rate (GB/s): one mib MiB buffer copied reps
+    times after one untimed copy, HIP events on the current stream."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(mib << 20, dtype=torch.uint8, device=device)
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    rate = reps * (mib << 20) / (a.elapsed_time(b) / 1e3) / 1e9
+    del src, dst
+    return rate
+
+
 def serving_bench(device, loads, seconds, streams=4, budget=1 << 30, per_key=16):
     """Poisson arrivals of decryption requests (parameter set 50/30/20 %,
     b uniform in 1..4096 ciphertexts, 10,000 device-resident keys split
@@ -561,6 +587,13 @@ def serving_bench(device, loads, seconds, streams=4, budget=1 << 30, per_key=16)
                    % (sum(counts.values()), per_key,
                       sum(p["u"].nbytes + p["v"].nbytes for p in pools.values()) / 1e9, gen_s),
            "seconds_per_load": seconds, "streams": streams, "budget_bytes": budget}
+    # the host link bounds the server: every ciphertext crosses it once
+    link = host_link_GBps(device)
+    mix = {1: 0.5, 3: 0.3, 5: 0.2}
+    per_dec = sum(f * 8 * ((SETS[p]["n"] + 63) // 64 + SETS[p]["n1"] * SETS[p]["n2"] // 64)
+                  for p, f in mix.items())
+    out["host_to_device_GBps"] = round(link, 2)
+    out["host_link_bound_decrypts_per_s"] = round(link * 1e9 / per_dec)
     for load in loads:
         reqs = serve.poisson_requests(load, seconds, counts, int(load) & 0xFFFF, pool_rows=rows)
         srv.checked = srv.mismatches = srv.launches = 0
@@ -679,6 +712,12 @@ def main():
             u = v = y = m = out = None
             r.update(kem_bench(hqc, pid, args.count, 0xC0DE + pid, dev))
         r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
+        cc = committed_counters("HQC-%d" % pid) if args.count == 65536 else None
+        if cc:
+            # issue-slot fraction of the VALU from the committed counters of
+            # this kernel source, beside the op-model fraction
+            r["valu_busy_counters"] = cc["valu_busy"]
+            r["valu_insts_per_decrypt"] = cc["valu_insts_per_item"]
         if pid in tuned:
             t = tuned[pid]
             r["autotune"] = {"tile": t["tile"], "grid": t["grid"], "ms": round(t["ms"], 4),
@@ -688,6 +727,8 @@ def main():
         results[pid] = r
         del u, v, y, m, out
         torch.cuda.empty_cache()
+        progress("HQC-%d: %.4f ms per launch, messages %s" % (pid, r["ms_mean"],
+                 "ok" if r["all_messages_recovered"] else "WRONG"))
 
     main_r = results[sets[0]]
     if not main_checks(results):
@@ -721,7 +762,8 @@ def main():
                                    for kk, vv in r.items()} for k, r in results.items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS,
-                     "traffic": measured_traffic() if (pid0 == 1 and args.count == 65536) else None,
+                     "traffic": ((committed_counters("HQC-%d" % pid0) or {}).get("traffic_bytes")
+                                 if args.count == 65536 else None),
                      "traffic_algorithmic": hbm_bytes(pid0) * args.count,
                      "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
                      "kernel_ms": main_r["ms_mean"]},
@@ -731,10 +773,16 @@ def main():
         line["batched_over_per_item"] = main_r["batched_over_per_item"]
     if not args.no_decode_stress:
         line["decode_stress"] = decode_stress_bench(hqc, dev)
+        progress("decoder stress: %.3f ms" % line["decode_stress"]["ms_median"])
+        cc = committed_counters("decode_mixed")
+        if cc:
+            line["decode_stress"]["valu_busy_counters"] = cc["valu_busy"]
+            line["decode_stress"]["valu_insts_per_word"] = cc["valu_insts_per_item"]
         if not line["decode_stress"]["all_messages_recovered"]:
             print("decoder stress: messages differ from the encoded ones", file=sys.stderr)
     if not args.no_serving:
         line["serving"] = serving_bench(dev, (1e5, 1e6, 1e7), args.serving_seconds)
+        progress("serving done")
         line["p99_latency_ms_serving_1e6"] = line["serving"]["1e+06"]["p99_ms"]
         if not serving_checks(line["serving"]):
             print("serving: served messages differ from the encrypted ones", file=sys.stderr)

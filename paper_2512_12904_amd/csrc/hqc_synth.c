@@ -166,7 +166,13 @@ static void *run_task(void *arg) {
 }
 
 static int run(task_t tmpl, size_t count, int nthreads) {
-  if (tmpl.sz.n <= 0 || tmpl.sz.n1 <= 0 || tmpl.sz.rho >= 1024) return -1;
+  const synth_sizes_t *s = &tmpl.sz;
+  /* every fixed-weight draw must be able to finish: weights at most their
+     bound, noise weights within one block and the position buffer */
+  if (s->n <= 0 || s->n1 <= 0 || s->n2 <= 0 || s->k < 0 || s->rho < 0 || s->rho >= 1024 ||
+      s->rho > s->n2 || s->delta < 0 || s->delta > s->n1 || s->w < 0 || s->w > s->n ||
+      s->wr < 0 || s->wr > s->n || s->we < 0 || s->we > s->n || (s->n1 * s->n2) % 64 != 0)
+    return -1;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   if ((size_t)nthreads > count) nthreads = count ? (int)count : 1;
