@@ -239,6 +239,26 @@ int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const ui
                          const uint64_t *v, uint8_t *key_out, void *workspace,
                          size_t workspace_bytes, size_t count);
 
+/* ---- Allocation-free decapsulation ----------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * hqc_kem_decaps_batch with its workspace taken from a fixed array of
+ * HQC_NOALLOC_SCRATCH_BYTES bytes that the library's code object holds on
+ * every device it runs on, until the process ends.  The call allocates
+ * nothing.  count is limited by that size: HQC_ERANGE unless
+ * hqc_kem_workspace_bytes(param_id, count) <= HQC_NOALLOC_SCRATCH_BYTES
+ * (69,041 HQC-1, 44,034 HQC-3 or 34,592 HQC-5 items).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads, before the earlier call's stream has passed it) race
+ * and give undefined keys; calls ordered on one stream are safe.  Nothing
+ * in the array needs to start at zero (every call writes what it reads).
+ * Other arguments, errors and results as hqc_kem_decaps_batch. */
+#define HQC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hqc_kem_decaps_batch_noalloc(const hqc_params_t *params, const uint64_t *h,
+                                 const uint64_t *s, const uint32_t *y, const uint8_t *sigma,
+                                 const uint64_t *u, const uint64_t *v, uint8_t *key_out,
+                                 size_t count);
+
 /* ---- Adaptive ring multiplication (Sec. III-B, threshold-aware
  * scheduling): out[i] = a[i] * b[i] in GF(2)[X]/(X^n - 1) for dense n-bit
  * rows (u_words words each; bits >= n of a and b ignored, of out zero).

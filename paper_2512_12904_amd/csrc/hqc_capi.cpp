@@ -256,8 +256,9 @@ int check_params(const hqc_params_t *p) {
 }
 
 // Validates one segment and fills its device descriptor.  Keyed segments
-// carry their key ids (count uint32) in s.y.
-int fill_segment(int op, const hqc_segment_t &s, hqc::SegDev *o) {
+// carry their key ids (count uint32) in s.y.  out_checked: m_out is memory
+// the library itself provides (sized already), not a caller's allocation.
+int fill_segment(int op, const hqc_segment_t &s, hqc::SegDev *o, bool out_checked = false) {
   hqc::SetInfo si;
   if (!hqc::set_info(s.param_id, &si) || s.reserved != 0) return HQC_EINVAL;
   if (s.count > HQC_MAX_COUNT) return HQC_ERANGE;
@@ -281,7 +282,7 @@ int fill_segment(int op, const hqc_segment_t &s, hqc::SegDev *o) {
         return HQC_EINVAL;
     }
   }
-  if (!in_device_allocation(s.m_out, c * si.k)) return HQC_EINVAL;
+  if (!out_checked && !in_device_allocation(s.m_out, c * si.k)) return HQC_EINVAL;
   o->u = s.u;
   o->v = s.v;
   o->y = op == hqc::OP_KEYED ? nullptr : s.y;
@@ -291,7 +292,7 @@ int fill_segment(int op, const hqc_segment_t &s, hqc::SegDev *o) {
 }
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, uint8_t *dbg = nullptr);
+                 const hqc_keystore_t *ks, uint8_t *dbg = nullptr, bool out_checked = false);
 
 }  // namespace
 
@@ -305,7 +306,7 @@ struct hqc_keystore {
 namespace {
 
 int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int nseg,
-                 const hqc_keystore_t *ks, uint8_t *dbg) {
+                 const hqc_keystore_t *ks, uint8_t *dbg, bool out_checked) {
   int rc = check_params(p);
   if (rc) return rc;
   if (!segs || nseg < 1 || nseg > 3) return HQC_EINVAL;
@@ -318,7 +319,7 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
     if (seen & (unsigned)pid_bit(segs[i].param_id)) return HQC_EINVAL;  // one per set
     seen |= (unsigned)pid_bit(segs[i].param_id);
     hqc::SegDev sd;
-    rc = fill_segment(op, segs[i], &sd);
+    rc = fill_segment(op, segs[i], &sd, out_checked);
     if (rc) return rc;
     if (sd.count == 0) continue;
     if (op == hqc::OP_KEYED) {
@@ -650,10 +651,12 @@ bool kem_layout(int pid, size_t count, KemLayout *o) {
   return true;
 }
 
-// shared checks of encaps / decaps; fills si and the workspace layout
+// shared checks of encaps / decaps; fills si and the workspace layout.
+// ws_own: the workspace is the library's own scratch (ws_bytes is its size).
 int kem_check(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
               const uint64_t *u, const uint64_t *v, const uint8_t *key_out, void *ws,
-              size_t ws_bytes, size_t count, hqc::SetInfo *si, KemLayout *lay) {
+              size_t ws_bytes, size_t count, hqc::SetInfo *si, KemLayout *lay,
+              bool ws_own = false) {
   int rc = check_params(params);
   if (rc) return rc;
   if (!hqc::set_info(params->param_id, si)) return HQC_EINVAL;
@@ -669,7 +672,58 @@ int kem_check(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
       !in_device_allocation(key_out, c * HQC_KEM_KEY_BYTES))
     return HQC_EINVAL;
   kem_layout(params->param_id, count, lay);
+  if (ws_own) return ws_bytes < lay->total ? HQC_ERANGE : HQC_OK;
   if (ws_bytes < lay->total || !in_device_allocation(ws, lay->total)) return HQC_EINVAL;
+  return HQC_OK;
+}
+
+// Decapsulation (decrypt, draws, re-encryption check, key) with the
+// workspace laid out as lay; ws_own as for kem_check.
+int kem_decaps(const hqc_params_t *params, const uint64_t *h, const uint64_t *s,
+               const uint32_t *y, const uint8_t *sigma, const uint64_t *u, const uint64_t *v,
+               uint8_t *key_out, void *workspace, size_t workspace_bytes, size_t count,
+               bool ws_own) {
+  hqc::SetInfo si;
+  KemLayout lay;
+  int rc = kem_check(params, h, s, u, v, key_out, workspace, workspace_bytes, count, &si, &lay,
+                     ws_own);
+  if (rc || count == 0) return rc;
+  if (!aligned(y, 4) || !in_device_allocation(y, count * (size_t)si.w * 4)) return HQC_EINVAL;
+  if (!aligned(sigma, 8) || !in_device_allocation(sigma, count * (size_t)si.k)) return HQC_EINVAL;
+  const int pid = params->param_id;
+  hipStream_t st = (hipStream_t)params->stream;
+  uint8_t *mp = (uint8_t *)workspace + lay.m_off;
+  uint32_t *ok = (uint32_t *)((char *)workspace + lay.ok_off);
+  uint32_t *draws = (uint32_t *)((char *)workspace + lay.draws_off);
+  // m' = Decrypt(y, (u, v)) into the workspace
+  hqc_segment_t sg;
+  std::memset(&sg, 0, sizeof sg);
+  sg.param_id = pid;
+  sg.count = count;
+  sg.u = u;
+  sg.v = v;
+  sg.y = y;
+  sg.m_out = mp;
+  rc = run_segments(hqc::OP_DECRYPT, params, &sg, 1, nullptr, nullptr, true);
+  if (rc) return rc;
+  hipError_t e = hqc::launch_kem_draws(pid, mp, draws, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  // re-encrypt m' and compare with (u, v)
+  hqc::EncArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.h = h;
+  a.s = s;
+  a.m = mp;
+  a.draws = draws;
+  a.draw_stride = hqc::kem_draw_stride(pid);
+  a.u_in = u;
+  a.v_in = v;
+  a.ok = ok;
+  a.count = (uint32_t)count;
+  rc = run_encrypt(hqc::ENC_CHECK, params, a);
+  if (rc) return rc;
+  e = hqc::launch_kem_key(pid, mp, sigma, ok, u, v, key_out, (uint32_t)count, st);
+  if (e != hipSuccess) return hip_fail(e);
   return HQC_OK;
 }
 
@@ -737,47 +791,20 @@ int hqc_kem_decaps_batch(const hqc_params_t *params, const uint64_t *h, const ui
                          const uint32_t *y, const uint8_t *sigma, const uint64_t *u,
                          const uint64_t *v, uint8_t *key_out, void *workspace,
                          size_t workspace_bytes, size_t count) {
-  hqc::SetInfo si;
-  KemLayout lay;
-  int rc = kem_check(params, h, s, u, v, key_out, workspace, workspace_bytes, count, &si, &lay);
-  if (rc || count == 0) return rc;
-  if (!aligned(y, 4) || !in_device_allocation(y, count * (size_t)si.w * 4)) return HQC_EINVAL;
-  if (!aligned(sigma, 8) || !in_device_allocation(sigma, count * (size_t)si.k)) return HQC_EINVAL;
-  const int pid = params->param_id;
-  hipStream_t st = (hipStream_t)params->stream;
-  uint8_t *mp = (uint8_t *)workspace + lay.m_off;
-  uint32_t *ok = (uint32_t *)((char *)workspace + lay.ok_off);
-  uint32_t *draws = (uint32_t *)((char *)workspace + lay.draws_off);
-  // m' = Decrypt(y, (u, v)) into the workspace
-  hqc_segment_t sg;
-  std::memset(&sg, 0, sizeof sg);
-  sg.param_id = pid;
-  sg.count = count;
-  sg.u = u;
-  sg.v = v;
-  sg.y = y;
-  sg.m_out = mp;
-  rc = run_segments(hqc::OP_DECRYPT, params, &sg, 1, nullptr);
-  if (rc) return rc;
-  hipError_t e = hqc::launch_kem_draws(pid, mp, draws, (uint32_t)count, st);
+  return kem_decaps(params, h, s, y, sigma, u, v, key_out, workspace, workspace_bytes, count,
+                    false);
+}
+
+int hqc_kem_decaps_batch_noalloc(const hqc_params_t *params, const uint64_t *h,
+                                 const uint64_t *s, const uint32_t *y, const uint8_t *sigma,
+                                 const uint64_t *u, const uint64_t *v, uint8_t *key_out,
+                                 size_t count) {
+  if (count == 0) return check_params(params);
+  void *scratch = nullptr;
+  hipError_t e = hqc::noalloc_scratch(&scratch);
   if (e != hipSuccess) return hip_fail(e);
-  // re-encrypt m' and compare with (u, v)
-  hqc::EncArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.h = h;
-  a.s = s;
-  a.m = mp;
-  a.draws = draws;
-  a.draw_stride = hqc::kem_draw_stride(pid);
-  a.u_in = u;
-  a.v_in = v;
-  a.ok = ok;
-  a.count = (uint32_t)count;
-  rc = run_encrypt(hqc::ENC_CHECK, params, a);
-  if (rc) return rc;
-  e = hqc::launch_kem_key(pid, mp, sigma, ok, u, v, key_out, (uint32_t)count, st);
-  if (e != hipSuccess) return hip_fail(e);
-  return HQC_OK;
+  return kem_decaps(params, h, s, y, sigma, u, v, key_out, scratch, HQC_NOALLOC_SCRATCH_BYTES,
+                    count, true);
 }
 
 // ---- adaptive ring multiplication ----------------------------------------------------

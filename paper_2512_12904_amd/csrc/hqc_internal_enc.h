@@ -50,6 +50,11 @@ hipError_t launch_kem_draws(int pid, const uint8_t *m, uint32_t *draws, uint32_t
 hipError_t launch_kem_key(int pid, const uint8_t *m, const uint8_t *sigma, const uint32_t *ok,
                           const uint64_t *u, const uint64_t *v, uint8_t *key, uint32_t count,
                           hipStream_t stream);
+// The device address, on the current device, of the library's fixed scratch
+// array (HQC_NOALLOC_SCRATCH_BYTES bytes, hqc_kem.hip), looked up once per
+// device; every caller on a device shares it.
+hipError_t noalloc_scratch(void **ptr);
+
 // Adaptive ring multiplication (hqc_ring.hip).  Workspace: a header for
 // count items, then the dense scratch of chunk_items items.
 size_t ring_workspace_bytes(int pid, size_t count, size_t chunk_items);

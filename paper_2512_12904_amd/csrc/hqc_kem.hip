@@ -14,9 +14,12 @@
 // (v_bitop3_b32).  Every item of a launch has the same length, so all loop
 // bounds and branches are uniform; data only flows through the lanes' own
 // state and loads at fixed offsets of their own rows.
+#include <map>
+#include <mutex>
 #include <utility>
 
 #include "hqc_device.h"
+#include "hqc_gpu.h"
 #include "hqc_internal_enc.h"
 
 namespace hqc {
@@ -306,6 +309,37 @@ hipError_t launch_kem_key(int pid, const uint8_t *m, const uint8_t *sigma, const
     case 3: return key_for<3>(m, sigma, ok, u, v, key, count, stream);
     default: return key_for<5>(m, sigma, ok, u, v, key, count, stream);
   }
+}
+
+// ---- fixed scratch for the allocation-free decapsulation ----------------------
+// A file-scope device array: the code object holds one instance per device,
+// for the life of the process.  Host code uses only the address that
+// hipGetSymbolAddress returns for the current device (the array's name in
+// host code is a host-side stand-in, not a device address).
+namespace {
+__device__ __align__(256) unsigned char scratch[HQC_NOALLOC_SCRATCH_BYTES];
+
+struct ScratchAddr {
+  std::mutex mu;
+  std::map<int, void *> ptr;  // device -> address of its scratch
+};
+ScratchAddr g_scratch;
+}  // namespace
+
+hipError_t noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch.mu);
+  auto it = g_scratch.ptr.find(dev);
+  if (it == g_scratch.ptr.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = g_scratch.ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
 }
 
 }  // namespace hqc

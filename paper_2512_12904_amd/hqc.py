@@ -32,7 +32,7 @@ EXPORTS = (
     "hqc_decrypt_mixed_keyed", "hqc_strerror",
     "hqc_last_hip_error", "hqc_default_grid", "hqc_shutdown", "hqc_keygen_batch",
     "hqc_encrypt_batch", "hqc_code_encode_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
-    "hqc_kem_decaps_batch", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
+    "hqc_kem_decaps_batch", "hqc_kem_decaps_batch_noalloc", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
     "hqc_ring_mul_batch", "hqc_autotune_decrypt", "hqc_tune_set", "hqc_tune_get",
     "hqc_tune_clear", "hqc_debug_bytes", "hqc_decrypt_debug",
 )
@@ -110,6 +110,8 @@ def lib():
                                            sz]
         L.hqc_kem_decaps_batch.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp,
                                            sz, sz]
+        L.hqc_kem_decaps_batch_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp,
+                                                   vp, sz]
         L.hqc_fixed_weight_batch.argtypes = [ctypes.POINTER(Params), vp, vp, sz]
         L.hqc_ring_workspace_bytes.restype = ctypes.c_size_t
         L.hqc_ring_workspace_bytes.argtypes = [ctypes.c_int, sz, sz]
@@ -440,6 +442,27 @@ def kem_decaps_batch(pid, h, s, y, sigma, u, v, key_out=None, workspace=None, gr
         _dev(key_out, torch.uint8, "key_out", (count, KEM_KEY_BYTES)),
         _dev(ws, torch.uint8, "workspace"), ws.numel(), count)
     _check(rc, "hqc_kem_decaps_batch")
+    return key_out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def kem_decaps_batch_noalloc(pid, h, s, y, sigma, u, v, key_out, grid=0, stream=None):
+    """kem_decaps_batch with the library's fixed scratch as workspace
+    (hqc_kem_decaps_batch_noalloc): allocates nothing, key_out is required."""
+    sz = sizes(pid)
+    count = u.shape[0]
+    p = _params(pid, 0, grid, stream)
+    rc = lib().hqc_kem_decaps_batch_noalloc(
+        ctypes.byref(p), _dev(h, torch.int64, "h", (count, sz["u_words"])),
+        _dev(s, torch.int64, "s", (count, sz["u_words"])),
+        _dev(y, torch.int32, "y", (count, sz["w"])),
+        _dev(sigma, torch.uint8, "sigma", (count, sz["k"])),
+        _dev(u, torch.int64, "u", (count, sz["u_words"])),
+        _dev(v, torch.int64, "v", (count, sz["v_words"])),
+        _dev(key_out, torch.uint8, "key_out", (count, KEM_KEY_BYTES)), count)
+    _check(rc, "hqc_kem_decaps_batch_noalloc")
     return key_out
 
 
