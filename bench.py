@@ -720,7 +720,9 @@ def main():
             r["valu_insts_per_decrypt"] = cc["valu_insts_per_item"]
         if pid in tuned:
             t = tuned[pid]
-            r["autotune"] = {"tile": t["tile"], "grid": t["grid"], "ms": round(t["ms"], 4),
+            r["autotune"] = {"shape": "AB"[t["shape"] - 1], "tile": t["tile"], "grid": t["grid"],
+                             "ms": round(t["ms"], 4),
+                             "default_shape": "AB"[t["heuristic_shape"] - 1],
                              "default_tile": t["heuristic_tile"], "default_grid": t["heuristic_grid"],
                              "default_ms": round(t["heuristic_ms"], 4),
                              "candidates": t["candidates"], "identical": bool(t["identical"])}
@@ -753,7 +755,8 @@ def main():
                                % (pid0, args.count), "param_set": "HQC-%d" % pid0,
                    "batch": args.count,
                    "launch": "hipGraph, persistent grid, %s" % (
-                       "tile %d x grid %d from the autotuner" % (tuned[pid0]["tile"], tuned[pid0]["grid"])
+                       "shape %s, tile %d x grid %d from the autotuner" % (
+                           "AB"[tuned[pid0]["shape"] - 1], tuned[pid0]["tile"], tuned[pid0]["grid"])
                        if pid0 in tuned else "tile %d / grid %d (0 = library default)" % (TILE, GRID))},
         "gpu": gpu_info(dev),
         "p50_launch_ms": main_r["ms_p50"],

@@ -92,6 +92,15 @@ typedef struct hqc_params {
   int32_t grid;     /* persistent workgroups; 0 = chosen by the library */
   int32_t tile;     /* items per workgroup tile, 1..64; 0 = chosen by the library.
                        Results never depend on grid or tile. */
+  int32_t shape;    /* kernel shape: 0 = chosen by the library, 1 = shape A, 2 =
+                       shape B (single-set HQC-1 or HQC-3 decryption, decoding
+                       and keyed decryption only; HQC_EINVAL elsewhere).
+                       A: every set's default (HQC-1: one RM block per lane,
+                       received words of four items in LDS; two wavefronts
+                       per SIMD).  B: every RM block on a lane pair, less LDS
+                       per wavefront (HQC-1: two items' received words;
+                       HQC-3: the received word over the doubled u), three
+                       wavefronts per SIMD.  Results never depend on it. */
 } hqc_params_t;
 
 /* One homogeneous part of a mixed-parameter batch (host struct). */
@@ -313,16 +322,19 @@ int hqc_default_grid(int param_id);
 void hqc_shutdown(void);
 
 /* ---- Launch-configuration autotuner ------------------------------------
- * The decryption kernels take two launch parameters that never change the
- * results: the persistent grid (workgroups) and the tile (ciphertexts per
- * workgroup tile, which also picks the Reed-Solomon mapping: two lanes per
- * word for tiles of at most 32, one lane per word above).  The library
- * keeps a table, per device, parameter set and batch-size bucket (the
- * power of two at or above count), of the configuration to use when a
- * single-set call leaves params->grid and params->tile at 0; without an
- * entry it uses the occupancy grid and tile = ceil(count / grid), at most 64.
- * Because the kernels' time does not depend on the data (constant time),
- * configurations can be timed on random inputs. */
+ * The decryption kernels take three launch parameters that never change the
+ * results: the kernel shape (params->shape: RM blocks per lane or per lane
+ * pair, LDS layout, wavefronts per SIMD), the persistent grid (workgroups)
+ * and the tile (ciphertexts per workgroup tile, which also picks the
+ * Reed-Solomon mapping: two lanes per word for tiles of at most 32, one
+ * lane per word above).  The library keeps a table, per device, parameter
+ * set and batch-size bucket (the power of two at or above count), of the
+ * configuration to use when a single-set call leaves params->grid,
+ * params->tile and params->shape at 0; without an entry it uses shape A
+ * (shape B for HQC-1 once count fills B's occupancy grid with tiles of 32),
+ * the occupancy grid and tile = ceil(count / grid), at most 64.  Because the
+ * kernels' time does not depend on the data (constant time), configurations
+ * can be timed on random inputs. */
 typedef struct hqc_tune_report {
   int32_t param_id;
   int32_t tile, grid;            /* chosen configuration (now in the table) */
@@ -332,9 +344,11 @@ typedef struct hqc_tune_report {
   int32_t candidates;            /* configurations timed */
   int32_t identical;             /* 1: every configuration gave byte-identical messages */
   uint64_t count;
+  int32_t shape;                 /* chosen shape (1 = A, 2 = B) */
+  int32_t heuristic_shape;       /* the built-in default's shape */
 } hqc_tune_report_t;
 
-/* Times candidate (tile, grid) pairs of the decryption kernel for param_id
+/* Times candidate (shape, tile, grid) triples of the decryption kernel for param_id
  * (1, 3 or 5) on count random ciphertexts (count in 1 .. 2^20): one untimed
  * launch each, whose messages must all be byte-identical, then reps rounds
  * that time every candidate once, on `stream` (NULL: null stream).  The
@@ -349,11 +363,12 @@ typedef struct hqc_tune_report {
 int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *stream,
                          hqc_tune_report_t *out);
 /* Sets the table entry of count's bucket on the current device (tile 1..64,
- * grid >= 1); tile = grid = 0 removes it.  HQC_EINVAL otherwise. */
-int hqc_tune_set(int param_id, size_t count, int tile, int grid);
-/* The entry used for a call of count items: *tile and *grid, or 0 and 0
- * when there is none.  HQC_EINVAL for a bad id or NULL pointers. */
-int hqc_tune_get(int param_id, size_t count, int *tile, int *grid);
+ * grid >= 1, shape 1 (A) or 2 (B, HQC-1 and HQC-3 only)); tile = grid =
+ * shape = 0 removes it.  HQC_EINVAL otherwise. */
+int hqc_tune_set(int param_id, size_t count, int tile, int grid, int shape);
+/* The entry used for a call of count items: *tile, *grid and *shape, or 0, 0
+ * and 0 when there is none.  HQC_EINVAL for a bad id or NULL pointers. */
+int hqc_tune_get(int param_id, size_t count, int *tile, int *grid, int *shape);
 /* Empties the table (all devices). */
 void hqc_tune_clear(void);
 

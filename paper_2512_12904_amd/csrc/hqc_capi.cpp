@@ -49,16 +49,16 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Grid {
   std::mutex mu;
-  std::map<std::tuple<int, int, unsigned>, int> cache;  // (device, op, mask) -> grid
+  std::map<std::tuple<int, int, unsigned, int>, int> cache;  // (device, op, mask, shape) -> grid
 };
 Grid g_grid;
 
-int default_grid(int op, unsigned mask, int *out) {
+int default_grid(int op, unsigned mask, int *out, int shape = 0) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
   std::lock_guard<std::mutex> lk(g_grid.mu);
-  auto key = std::make_tuple(dev, op, mask);
+  auto key = std::make_tuple(dev, op, mask, shape);
   auto it = g_grid.cache.find(key);
   if (it != g_grid.cache.end()) {
     *out = it->second;
@@ -67,8 +67,8 @@ int default_grid(int op, unsigned mask, int *out) {
   int cus = 0, per_cu = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hqc::kernel_ptr(op, mask), 64,
-                                                   hqc::lds_bytes_for(mask));
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hqc::kernel_ptr(op, mask, shape), 64,
+                                                   hqc::lds_bytes_for(mask, shape));
   if (e != hipSuccess) return hip_fail(e);
   if (per_cu < 1) per_cu = 1;
   *out = cus * per_cu;
@@ -80,11 +80,13 @@ int default_grid(int op, unsigned mask, int *out) {
 struct GraphKey {
   int op;
   unsigned mask;
+  int shape;
   int grid;
   int device;
   std::vector<unsigned char> args;
   bool operator<(const GraphKey &o) const {
-    return std::tie(op, mask, grid, device, args) < std::tie(o.op, o.mask, o.grid, o.device, o.args);
+    return std::tie(op, mask, shape, grid, device, args) <
+           std::tie(o.op, o.mask, o.shape, o.grid, o.device, o.args);
   }
 };
 struct GraphCache {
@@ -102,11 +104,12 @@ void clear_graphs_locked() {
   g_graphs.entries.clear();
 }
 
-int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream_t st) {
+int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream_t st,
+                 int shape) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
-  GraphKey key{op, mask, grid, dev, std::vector<unsigned char>(sizeof a)};
+  GraphKey key{op, mask, shape, grid, dev, std::vector<unsigned char>(sizeof a)};
   std::memcpy(key.args.data(), &a, sizeof a);
   std::lock_guard<std::mutex> lk(g_graphs.mu);
   auto it = g_graphs.entries.find(key);
@@ -120,10 +123,10 @@ int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream
     void *params[] = {&copy};
     hipKernelNodeParams np;
     std::memset(&np, 0, sizeof np);
-    np.func = const_cast<void *>(hqc::kernel_ptr(op, mask));
+    np.func = const_cast<void *>(hqc::kernel_ptr(op, mask, shape));
     np.gridDim = dim3((unsigned)grid);
     np.blockDim = dim3(64);
-    np.sharedMemBytes = (unsigned)hqc::lds_bytes_for(mask);
+    np.sharedMemBytes = (unsigned)hqc::lds_bytes_for(mask, shape);
     np.kernelParams = params;
     hipGraphNode_t node;
     e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &np);
@@ -142,9 +145,12 @@ int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream
 // Tuned launch configurations: (device, parameter set, batch-size bucket)
 // -> (tile, grid), filled by hqc_tune_set / hqc_autotune_decrypt.  The
 // bucket of a count is the exponent of the power of two at or above it.
+struct TunedEntry {
+  int tile, grid, shape;  // shape: 0 or 1 (the kernel shape itself)
+};
 struct Tuned {
   std::mutex mu;
-  std::map<std::tuple<int, int, int>, std::pair<int, int>> table;
+  std::map<std::tuple<int, int, int>, TunedEntry> table;
 };
 Tuned g_tuned;
 
@@ -164,13 +170,14 @@ int device_or_none() {
   return dev;
 }
 
-bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid) {
+bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid, int *shape) {
   const auto key = std::make_tuple(device_or_none(), pid, count_bucket(count));
   std::lock_guard<std::mutex> lk(g_tuned.mu);
   auto it = g_tuned.table.find(key);
   if (it == g_tuned.table.end()) return false;
-  *tile = it->second.first;
-  *grid = it->second.second;
+  *tile = it->second.tile;
+  *grid = it->second.grid;
+  *shape = it->second.shape;
   return true;
 }
 
@@ -192,18 +199,38 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
   for (uint32_t s = 0; s < a.nseg; ++s) items += a.seg[s].count;
   if (items == 0) return HQC_OK;
   int grid = p->grid;
-  int full = 0;
-  {
-    int rc = default_grid(op, mask, &full);
-    if (rc) return rc;
-  }
   uint32_t tile = (uint32_t)p->tile;
-  if (grid <= 0 && tile == 0 && (mask == 1u || mask == 2u || mask == 4u)) {
-    int tt = 0, tg = 0;
-    if (tuned_lookup(mask == 1u ? 1 : mask == 2u ? 3 : 5, items, &tt, &tg)) {
+  // kernel shape: the caller's (1 = shape 0, 2 = shape 1), else the tuned
+  // table's, else the built-in choice
+  int shape = p->shape - 1;
+  if (shape == 1 && !hqc::shape_exists(op, mask, 1)) return HQC_EINVAL;
+  bool tuned = false;
+  if (grid <= 0 && tile == 0 && p->shape == 0 && (mask == 1u || mask == 2u || mask == 4u)) {
+    int tt = 0, tg = 0, ts = 0;
+    if (tuned_lookup(mask == 1u ? 1 : mask == 2u ? 3 : 5, items, &tt, &tg, &ts) &&
+        hqc::shape_exists(op, mask, ts)) {
       tile = (uint32_t)tt;
       grid = tg;
+      shape = ts;
+      tuned = true;
     }
+  }
+  if (shape < 0) {
+    // built-in: HQC-1's shape 1 once the batch fills its larger occupancy
+    // grid with tiles of 32 items (measured faster there, slower below)
+    shape = 0;
+    if (mask == 1u && hqc::shape_exists(op, mask, 1)) {
+      int g1 = 0;
+      int rc = default_grid(op, mask, &g1, 1);
+      if (rc) return rc;
+      if (items >= 32ull * (uint64_t)g1) shape = 1;
+    }
+  }
+  (void)tuned;
+  int full = 0;
+  {
+    int rc = default_grid(op, mask, &full, shape);
+    if (rc) return rc;
   }
   if (grid <= 0) grid = full;
   if (tile == 0) {
@@ -235,20 +262,21 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
         if (sg.y) o.y = sg.y + (size_t)i * si.w;
         if (sg.key_ids) o.key_ids = sg.key_ids + i;
         o.m = sg.m + (size_t)i * si.k;
-        hipError_t e = hqc::launch(op, (unsigned)pid_bit(sg.pid), one, 1, st);
+        hipError_t e = hqc::launch(op, (unsigned)pid_bit(sg.pid), one, 1, st, 0);
         if (e != hipSuccess) return hip_fail(e);
       }
     }
     return HQC_OK;
   }
-  if (p->flags & HQC_F_GRAPH) return launch_graph(op, mask, a, grid, st);
-  hipError_t e = hqc::launch(op, mask, a, grid, st);
+  if (p->flags & HQC_F_GRAPH) return launch_graph(op, mask, a, grid, st, shape);
+  hipError_t e = hqc::launch(op, mask, a, grid, st, shape);
   if (e != hipSuccess) return hip_fail(e);
   return HQC_OK;
 }
 
 int check_params(const hqc_params_t *p) {
   if (!p || p->tile < 0 || p->tile > 64) return HQC_EINVAL;
+  if (p->shape < 0 || p->shape > 2) return HQC_EINVAL;
   if (p->flags & ~(HQC_F_PER_ITEM_LAUNCH | HQC_F_GRAPH)) return HQC_EINVAL;
   if ((p->flags & HQC_F_PER_ITEM_LAUNCH) && (p->flags & HQC_F_GRAPH)) return HQC_EINVAL;
   if (p->grid < 0) return HQC_EINVAL;
@@ -295,6 +323,12 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
                  const hqc_keystore_t *ks, uint8_t *dbg = nullptr, bool out_checked = false);
 
 }  // namespace
+
+namespace hqc {
+int occupancy_grid(int op, unsigned mask, int shape, int *out) {
+  return default_grid(op, mask, out, shape);
+}
+}  // namespace hqc
 
 struct hqc_keystore {
   size_t cap[3];
@@ -893,23 +927,28 @@ void hqc_shutdown(void) {
   clear_graphs_locked();
 }
 
-int hqc_tune_set(int param_id, size_t count, int tile, int grid) {
+int hqc_tune_set(int param_id, size_t count, int tile, int grid, int shape) {
   if (!pid_bit(param_id) || count == 0 || count > HQC_MAX_COUNT) return HQC_EINVAL;
-  const bool erase = tile == 0 && grid == 0;
-  if (!erase && (tile < 1 || tile > 64 || grid < 1)) return HQC_EINVAL;
+  const bool erase = tile == 0 && grid == 0 && shape == 0;
+  if (!erase && (tile < 1 || tile > 64 || grid < 1 || shape < 1 || shape > 2)) return HQC_EINVAL;
+  if (shape == 2 && !hqc::shape_exists(hqc::OP_DECRYPT, (unsigned)pid_bit(param_id), 1))
+    return HQC_EINVAL;
   const auto key = std::make_tuple(device_or_none(), param_id, count_bucket(count));
   std::lock_guard<std::mutex> lk(g_tuned.mu);
   if (erase)
     g_tuned.table.erase(key);
   else
-    g_tuned.table[key] = std::make_pair(tile, grid);
+    g_tuned.table[key] = TunedEntry{tile, grid, shape - 1};
   return HQC_OK;
 }
 
-int hqc_tune_get(int param_id, size_t count, int *tile, int *grid) {
-  if (!pid_bit(param_id) || !tile || !grid || count == 0 || count > HQC_MAX_COUNT)
+int hqc_tune_get(int param_id, size_t count, int *tile, int *grid, int *shape) {
+  if (!pid_bit(param_id) || !tile || !grid || !shape || count == 0 || count > HQC_MAX_COUNT)
     return HQC_EINVAL;
-  if (!tuned_lookup(param_id, count, tile, grid)) *tile = *grid = 0;
+  if (tuned_lookup(param_id, count, tile, grid, shape))
+    *shape += 1;
+  else
+    *tile = *grid = *shape = 0;
   return HQC_OK;
 }
 

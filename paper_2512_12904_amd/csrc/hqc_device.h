@@ -24,7 +24,13 @@ constexpr int odd_dword_stride(int b) {
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <int ID> struct Geo {
+// Kernel shapes of the decryption kernels (SH, a tuning knob; results never
+// depend on it): shape 0 for every set, and shape 1 for HQC-1 and HQC-3, in
+// which every RM block is decoded on a lane pair and less LDS per wavefront
+// allows three wavefronts per SIMD instead of two.  Key generation and
+// encryption use shape 0's sizes.
+template <int ID, int SH = 0> struct Geo {
+  static_assert(SH == 0 || (SH == 1 && ID != 5), "shape 1 exists for HQC-1 and HQC-3");
   using S = Set<ID>;
   static constexpr int n = S::n, n1 = S::n1, n2 = S::n2, k = S::k, w = S::w;
   static constexpr int MULT = n2 / 128;
@@ -41,19 +47,22 @@ template <int ID> struct Geo {
   static constexpr int RB = n1 * BSTR;               // received-word dwords
   static constexpr int YREG = (w + 63) / 64;         // VGPRs holding y
   static constexpr int SSTR = odd_dword_stride(n1);  // symbol-table row (bytes)
-  // HQC-5 runs a tile as sub-tiles of at most 32 items (two lanes per
-  // Reed-Solomon word) and builds the received word over the doubled u once
-  // the product is in registers, so that one wavefront fits in 20 KiB of LDS
-  // (eight wavefronts per CU)
-  static constexpr bool COMPACT = ID == 5;
+  // HQC-5 (and HQC-3 in shape 1) runs a tile as sub-tiles of at most 32
+  // items (two lanes per Reed-Solomon word) and builds the received word over
+  // the doubled u once the product is in registers, so that one wavefront
+  // fits in 20 KiB of LDS (eight wavefronts per CU; HQC-3 shape 1: 11 KiB)
+  static constexpr bool COMPACT = ID == 5 || (ID == 3 && SH == 1);
   static constexpr int TROWS = COMPACT ? 32 : 64;    // items per (sub-)tile
   static constexpr int RB_OFF = COMPACT ? 0 : U2;    // dword offset of the received word
   // HQC-1 keeps the received words of RMG = 4 items and RM-decodes their
-  // 4 x 46 = 184 blocks in 3 passes of 64 lanes instead of 4 passes of 46
-  static constexpr int RMG = ID == 1 ? 4 : 1;
-  // HQC-5 decodes each RM block on a lane pair: its 90 blocks take 3 passes
-  // of 32 pairs (1.5 full passes) instead of 2 passes of 64 lanes
-  static constexpr bool PAIR_RM = ID == 5;
+  // 4 x 46 = 184 blocks in 3 passes of 64 lanes instead of 4 passes of 46;
+  // in shape 1 (lane-pair blocks) 2 items, 92 blocks in 3 passes of 32 pairs
+  static constexpr int RMG = ID == 1 ? (SH == 1 ? 2 : 4) : 1;
+  // HQC-5 (and shape 1) decodes each RM block on a lane pair: HQC-5's 90
+  // blocks take 3 passes of 32 pairs (1.5 full passes) instead of 2 passes
+  // of 64 lanes
+  static constexpr bool PAIR_RM = ID == 5 || SH == 1;
+  static constexpr int WAVES = SH == 1 ? 3 : 2;      // wavefronts per SIMD the kernel is built for
   static constexpr int A_BYTES =
       (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
@@ -65,6 +74,7 @@ template <int ID> struct Geo {
   static_assert(n1 * n2 % 64 == 0, "v is a whole number of words");
   static_assert(64 * R >= W32, "lanes cover the product");
   static_assert(TD + k == n1 && n1 < 255, "message positions");
+  static_assert(LDS_BYTES * 4 * WAVES <= 160 * 1024, "LDS of the wavefronts per CU");
 };
 
 // ---- GF(2^8) tables, x^8 + x^4 + x^3 + x^2 + 1, alpha = x ------------------

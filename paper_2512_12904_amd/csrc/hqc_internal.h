@@ -41,7 +41,7 @@ struct KArgs {
 struct SetInfo {
   int n, n1, n2, k, delta, w, mult;
   int u_words, v_words;
-  size_t lds_bytes;  // dynamic LDS one workgroup needs for this set
+  size_t lds_bytes;  // dynamic LDS one workgroup needs for this set (shape 0)
   // per-item intermediates of a debug launch, at these byte offsets: the
   // received word v + u*y (n1*n2 bits, little-endian dwords), the RM
   // symbols (n1), the syndromes S_1..S_2delta, Lambda (2 delta + 1
@@ -53,8 +53,15 @@ struct SetInfo {
 bool set_info(int pid, SetInfo *out);
 
 // mask: bit 0 = HQC-1, bit 1 = HQC-3, bit 2 = HQC-5 present in the launch.
-const void *kernel_ptr(int op, unsigned mask);
-size_t lds_bytes_for(unsigned mask);
-hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream);
+// shape: the kernel shape (0, or 1 for single-set HQC-1 / HQC-3 kernels
+// other than the debug one); kernel_ptr returns NULL where it does not exist.
+const void *kernel_ptr(int op, unsigned mask, int shape);
+size_t lds_bytes_for(unsigned mask, int shape);
+bool shape_exists(int op, unsigned mask, int shape);
+hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream,
+                  int shape);
+// the occupancy grid (CUs x resident workgroups) of a kernel on the current
+// device, cached (hqc_capi.cpp)
+int occupancy_grid(int op, unsigned mask, int shape, int *out);
 
 }  // namespace hqc

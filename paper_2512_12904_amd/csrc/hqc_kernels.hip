@@ -262,9 +262,9 @@ template <int ID> struct ItemRegs {
   uint32_t y[G::YREG];
 };
 
-template <int ID, int OP>
+template <int ID, int OP, int SH>
 __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRegs<ID> &r) {
-  using G = Geo<ID>;
+  using G = Geo<ID, SH>;
   using IR = ItemRegs<ID>;
   const int lane = lane_id();
   const uint32_t *vsrc = (const uint32_t *)((OP == OP_DECODE ? sg.u : sg.v) +
@@ -301,11 +301,11 @@ __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRe
 // The received word of one item from its registers r; once r is consumed
 // (before the product), the next item's loads are issued into r when
 // `next` is set, so that they overlap this item's product and RM passes.
-template <int ID, int OP>
+template <int ID, int OP, int SH>
 __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, uint32_t *rb,
                                               const uint32_t *vsrc, const SegDev &sg,
                                               uint32_t next_item, bool next) {
-  using G = Geo<ID>;
+  using G = Geo<ID, SH>;
   using IR = ItemRegs<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
@@ -318,7 +318,7 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
     }
   }
   if constexpr (OP == OP_DECODE) {
-    if (next) prefetch<ID, OP>(sg, next_item, r);
+    if (next) prefetch<ID, OP, SH>(sg, next_item, r);
     return;
   }
 
@@ -327,7 +327,7 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
   build_doubled_regs<ID, IR::UREG>(u2, r.u);
   uint32_t shreg[G::YREG];
   window_shifts<ID, G::YREG>(r.y, shreg);
-  if (next) prefetch<ID, OP>(sg, next_item, r);
+  if (next) prefetch<ID, OP, SH>(sg, next_item, r);
   wave_sync();
 
   // S1: product, R output dwords per lane
@@ -965,10 +965,10 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
   }
 }
 
-template <int ID, int OP>
+template <int ID, int OP, int SH>
 __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
                                         GfTab exp4, GfTab log4) {
-  using G = Geo<ID>;
+  using G = Geo<ID, SH>;
   const int lane = lane_id();
   uint8_t *sym = (uint8_t *)lds + G::A_BYTES;
   // the next item's u, v and y are loaded into VGPRs while this one's RM
@@ -976,17 +976,17 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   // layout (HQC-5) loads each item when it starts, leaving the latency to
   // the other wavefronts on the SIMD
   ItemRegs<ID> regs;
-  if constexpr (!G::COMPACT) prefetch<ID, OP>(sg, item0, regs);
+  if constexpr (!G::COMPACT) prefetch<ID, OP, SH>(sg, item0, regs);
   int passes = 0;  // RM passes done for the current group
   for (int it = 0; it < nt; ++it) {
     const uint32_t cur = item0 + (uint32_t)it;
     const int gi = it % G::RMG;  // slot of this item's received word
-    if constexpr (G::COMPACT) prefetch<ID, OP>(sg, cur, regs);
+    if constexpr (G::COMPACT) prefetch<ID, OP, SH>(sg, cur, regs);
     // HQC-1 issues the next item's loads before this item's product (its
     // product is short: the loads would not be covered by RM passes alone);
     // HQC-3 after it (measured 1 % faster there)
     constexpr bool EARLY = ID == 1;
-    received_word<ID, OP>(regs, lds, lds + G::RB_OFF + gi * G::RB,
+    received_word<ID, OP, SH>(regs, lds, lds + G::RB_OFF + gi * G::RB,
                           (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS), sg, cur + 1,
                           EARLY && it + 1 < nt);
     wave_sync();
@@ -995,7 +995,7 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
       uint32_t *dst = (uint32_t *)(sg.dbg + (size_t)cur * G::DBG_BYTES);
       for (int d = lane; d < G::W32; d += 64) dst[d] = rb[d + d / G::BLK];
     }
-    if (!G::COMPACT && !EARLY && it + 1 < nt) prefetch<ID, OP>(sg, cur + 1, regs);
+    if (!G::COMPACT && !EARLY && it + 1 < nt) prefetch<ID, OP, SH>(sg, cur + 1, regs);
     {
       // the group's blocks, flat index q n1 + b for block b of slot q, are
       // decoded BPP at a time (one lane or one lane pair each) as soon as the
@@ -1052,22 +1052,29 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   wave_sync();
 }
 
-// a tile of nt <= 64 items; HQC-5 takes it 32 items at a time
-template <int ID, int OP>
+// a tile of nt <= 64 items; the compact layout takes it 32 items at a time
+template <int ID, int OP, int SH>
 __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
                                          GfTab exp4, GfTab log4) {
-  using G = Geo<ID>;
+  using G = Geo<ID, SH>;
   if constexpr (G::COMPACT) {
     for (int s0 = 0; s0 < nt; s0 += G::TROWS)
-      run_sub<ID, OP>(sg, item0 + (uint32_t)s0, nt - s0 < G::TROWS ? nt - s0 : G::TROWS, lds,
-                      exp4, log4);
+      run_sub<ID, OP, SH>(sg, item0 + (uint32_t)s0, nt - s0 < G::TROWS ? nt - s0 : G::TROWS, lds,
+                          exp4, log4);
   } else {
-    run_sub<ID, OP>(sg, item0, nt, lds, exp4, log4);
+    run_sub<ID, OP, SH>(sg, item0, nt, lds, exp4, log4);
   }
 }
 
-template <int OP, unsigned MASK>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hqc_kernel(KArgs a) {
+// shape 1 exists for single-set HQC-1 and HQC-3 kernels
+constexpr int kernel_waves(unsigned mask, int sh) {
+  return sh == 1 ? (mask == 1u ? Geo<1, 1>::WAVES : Geo<3, 1>::WAVES) : 2;
+}
+
+template <int OP, unsigned MASK, int SH>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kernel_waves(MASK, SH)))) void
+hqc_kernel(KArgs a) {
+  static_assert(SH == 0 || MASK == 1u || MASK == 2u, "shape 1: HQC-1 or HQC-3 alone");
   extern __shared__ uint32_t lds[];
   const GfTab exp4 = gf_exp_tab();
   const GfTab log4 = gf_log_tab();
@@ -1079,22 +1086,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void hq
     const uint32_t item0 = (unit - sg.first) * a.tile;
     const uint32_t left = sg.count - item0;
     const int nt = (int)(left < a.tile ? left : a.tile);
-    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP>(sg, item0, nt, lds, exp4, log4);
-    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP>(sg, item0, nt, lds, exp4, log4);
-    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP, (MASK == 1u ? SH : 0)>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP, (MASK == 2u ? SH : 0)>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP, 0>(sg, item0, nt, lds, exp4, log4);
   }
 }
 
 template <int OP>
-const void *kernel_for_mask(unsigned mask) {
+const void *kernel_for_mask(unsigned mask, int shape) {
+  if (shape == 1) {
+    // debug launches run shape 0 only
+    if constexpr (OP == OP_DEBUG) return nullptr;
+    else if (mask == 1u) return (const void *)&hqc_kernel<OP, 1, 1>;
+    else if (mask == 2u) return (const void *)&hqc_kernel<OP, 2, 1>;
+    return nullptr;
+  }
   switch (mask) {
-    case 1: return (const void *)&hqc_kernel<OP, 1>;
-    case 2: return (const void *)&hqc_kernel<OP, 2>;
-    case 4: return (const void *)&hqc_kernel<OP, 4>;
+    case 1: return (const void *)&hqc_kernel<OP, 1, 0>;
+    case 2: return (const void *)&hqc_kernel<OP, 2, 0>;
+    case 4: return (const void *)&hqc_kernel<OP, 4, 0>;
     default:
       // debug launches carry one parameter set: no mixed-set debug kernel
       if constexpr (OP == OP_DEBUG) return nullptr;
-      else return (const void *)&hqc_kernel<OP, 7>;
+      else return (const void *)&hqc_kernel<OP, 7, 0>;
   }
 }
 
@@ -1128,17 +1142,22 @@ bool set_info(int pid, SetInfo *out) {
   }
 }
 
-const void *kernel_ptr(int op, unsigned mask) {
+const void *kernel_ptr(int op, unsigned mask, int shape) {
   if (mask != 1 && mask != 2 && mask != 4) mask = 7;
   switch (op) {
-    case OP_DECRYPT: return kernel_for_mask<OP_DECRYPT>(mask);
-    case OP_DECODE: return kernel_for_mask<OP_DECODE>(mask);
-    case OP_DEBUG: return kernel_for_mask<OP_DEBUG>(mask);
-    default: return kernel_for_mask<OP_KEYED>(mask);
+    case OP_DECRYPT: return kernel_for_mask<OP_DECRYPT>(mask, shape);
+    case OP_DECODE: return kernel_for_mask<OP_DECODE>(mask, shape);
+    case OP_DEBUG: return kernel_for_mask<OP_DEBUG>(mask, shape);
+    default: return kernel_for_mask<OP_KEYED>(mask, shape);
   }
 }
 
-size_t lds_bytes_for(unsigned mask) {
+size_t lds_bytes_for(unsigned mask, int shape) {
+  if (shape == 1) {
+    if (mask == 1u) return Geo<1, 1>::LDS_BYTES;
+    if (mask == 2u) return Geo<3, 1>::LDS_BYTES;
+    return 0;
+  }
   size_t b = 0;
   SetInfo si;
   if (mask & 1u) { set_info(1, &si); b = si.lds_bytes > b ? si.lds_bytes : b; }
@@ -1147,11 +1166,17 @@ size_t lds_bytes_for(unsigned mask) {
   return b;
 }
 
-hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream) {
-  const void *fn = kernel_ptr(op, mask);
+bool shape_exists(int op, unsigned mask, int shape) {
+  return kernel_ptr(op, mask, shape) != nullptr;
+}
+
+hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream, int shape) {
+  const void *fn = kernel_ptr(op, mask, shape);
+  if (!fn) return hipErrorInvalidDeviceFunction;
   KArgs copy = a;
   void *args[] = {&copy};
-  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), args, lds_bytes_for(mask), stream);
+  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), args, lds_bytes_for(mask, shape),
+                         stream);
 }
 
 }  // namespace hqc

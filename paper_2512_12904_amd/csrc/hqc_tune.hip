@@ -1,10 +1,11 @@
 // hqc_tune.hip -- launch-configuration autotuner of the decryption kernel
 // (hqc_autotune_decrypt in include/hqc_gpu.h).
 //
-// Candidates are (tile, grid) pairs: tiles of 1 .. 64 ciphertexts (the
-// tile also picks the Reed-Solomon mapping, two lanes per word up to 32)
-// and grids of 1/2 .. 3/2 of the occupancy grid, or one tile per workgroup
-// when a batch has fewer tiles than half that grid.  Each is launched once
+// Candidates are (shape, tile, grid) triples: the kernel shapes the set has
+// (A; B for HQC-1 and HQC-3), tiles of 1 .. 64 ciphertexts (the tile also
+// picks the Reed-Solomon mapping, two lanes per word up to 32) and grids of
+// 1/2 .. 3/2 of that shape's occupancy grid, or one tile per workgroup when
+// a batch has fewer tiles than half that grid.  Each is launched once
 // untimed and its messages compared byte for byte with those of the
 // built-in default; then `reps` rounds time every candidate once per round
 // with HIP events on the caller's stream (so drift during the search hits
@@ -19,6 +20,7 @@
 #include <vector>
 
 #include "hqc_gpu.h"
+#include "hqc_internal.h"
 
 namespace {
 
@@ -65,9 +67,14 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
   hqc_sizes_t sz;
   if (hqc_sizes(param_id, &sz) != HQC_OK) return HQC_EINVAL;
   if (count > ((size_t)1 << 20)) return HQC_ERANGE;
-  const int full = hqc_default_grid(param_id);
-  if (full < 0) return full;
-  if (full == 0) return HQC_EHIP;
+  const unsigned mask = param_id == 1 ? 1u : param_id == 3 ? 2u : 4u;
+  const int nshape = hqc::shape_exists(hqc::OP_DECRYPT, mask, 1) ? 2 : 1;
+  int full[2] = {0, 0};  // occupancy grid of each shape
+  for (int sh = 0; sh < nshape; ++sh) {
+    const int rc = hqc::occupancy_grid(hqc::OP_DECRYPT, mask, sh, &full[sh]);
+    if (rc != HQC_OK) return rc;
+    if (full[sh] <= 0) return HQC_EHIP;
+  }
   hipStream_t st = (hipStream_t)stream;
 
   Buffers B;
@@ -85,24 +92,35 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
                      0x7E59ull + param_id);
   if (hipGetLastError() != hipSuccess) return HQC_EHIP;
 
-  // the built-in default first: the occupancy grid and enough tiles for it
-  const int h_tile = (int)std::min<size_t>(64, std::max<size_t>(1, (count + full - 1) / full));
-  std::vector<std::pair<int, int>> cand{{h_tile, full}};
+  // the built-in default first (the library's choice for this count: shape
+  // B for HQC-1 once the batch fills B's grid with tiles of 32, else A; the
+  // occupancy grid and enough tiles for it)
+  const int h_shape = (mask == 1u && nshape == 2 && count >= 32 * (size_t)full[1]) ? 1 : 0;
+  const int h_full = full[h_shape];
+  const int h_tile = (int)std::min<size_t>(64, std::max<size_t>(1, (count + h_full - 1) / h_full));
+  struct Cand {
+    int shape, tile, grid;
+    bool operator==(const Cand &o) const {
+      return shape == o.shape && tile == o.tile && grid == o.grid;
+    }
+  };
+  std::vector<Cand> cand{{h_shape, h_tile, h_full}};
   const int tiles[] = {1, 2, 4, 8, 16, 24, 32, 40, 48, 64};
   const int gnum[] = {2, 3, 4, 5, 6};  // grid = full * gnum / 4
-  auto add = [&](int t, int grid) {
-    if (std::find(cand.begin(), cand.end(), std::make_pair(t, grid)) == cand.end())
-      cand.emplace_back(t, grid);
+  auto add = [&](int sh, int t, int grid) {
+    const Cand c{sh, t, grid};
+    if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
   };
-  for (int t : tiles) {
-    const size_t ntiles = (count + (size_t)t - 1) / (size_t)t;
-    for (int g : gnum) {
-      const int grid = std::max(1, full * g / 4);
-      if ((size_t)grid <= ntiles) add(t, grid);  // a larger grid would be clipped
+  for (int sh = 0; sh < nshape; ++sh)
+    for (int t : tiles) {
+      const size_t ntiles = (count + (size_t)t - 1) / (size_t)t;
+      for (int g : gnum) {
+        const int grid = std::max(1, full[sh] * g / 4);
+        if ((size_t)grid <= ntiles) add(sh, t, grid);  // a larger grid would be clipped
+      }
+      // fewer tiles than half the occupancy grid: one tile per workgroup
+      if (ntiles < (size_t)std::max(1, full[sh] / 2)) add(sh, t, (int)ntiles);
     }
-    // fewer tiles than half the occupancy grid: one tile per workgroup
-    if (ntiles < (size_t)std::max(1, full / 2)) add(t, (int)ntiles);
-  }
 
   std::vector<uint8_t> ref(nm), got(nm);
   std::vector<hqc_params_t> par(cand.size());
@@ -112,8 +130,9 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
     std::memset(&p, 0, sizeof p);
     p.param_id = param_id;
     p.stream = stream;
-    p.tile = cand[c].first;
-    p.grid = cand[c].second;
+    p.tile = cand[c].tile;
+    p.grid = cand[c].grid;
+    p.shape = cand[c].shape + 1;
     const int rc = hqc_decrypt_batch(&p, B.u, B.v, B.y, B.m, count);
     if (rc != HQC_OK) return rc;
     if (hipMemcpyAsync(got.data(), B.m, nm, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -150,17 +169,20 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
   if (med[best] > 0.99f * med[0]) best = 0;
   // a configuration that changed the messages is never stored
   if (identical) {
-    const int rc = hqc_tune_set(param_id, count, cand[best].first, cand[best].second);
+    const int rc = hqc_tune_set(param_id, count, cand[best].tile, cand[best].grid,
+                                cand[best].shape + 1);
     if (rc != HQC_OK) return rc;
   }
   std::memset(out, 0, sizeof *out);
   out->param_id = param_id;
   out->count = count;
-  out->tile = cand[best].first;
-  out->grid = cand[best].second;
+  out->tile = cand[best].tile;
+  out->grid = cand[best].grid;
+  out->shape = cand[best].shape + 1;
   out->ms = med[best];
-  out->heuristic_tile = cand[0].first;
-  out->heuristic_grid = cand[0].second;
+  out->heuristic_tile = cand[0].tile;
+  out->heuristic_grid = cand[0].grid;
+  out->heuristic_shape = cand[0].shape + 1;
   out->heuristic_ms = med[0];
   out->candidates = (int32_t)cand.size();
   out->identical = identical;

@@ -56,7 +56,7 @@ class Sizes(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("param_id", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("grid", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("shape", ctypes.c_int32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -64,7 +64,8 @@ class TuneReport(ctypes.Structure):
                 ("ms", ctypes.c_float), ("heuristic_tile", ctypes.c_int32),
                 ("heuristic_grid", ctypes.c_int32), ("heuristic_ms", ctypes.c_float),
                 ("candidates", ctypes.c_int32), ("identical", ctypes.c_int32),
-                ("count", ctypes.c_uint64)]
+                ("count", ctypes.c_uint64), ("shape", ctypes.c_int32),
+                ("heuristic_shape", ctypes.c_int32)]
 
 
 class Segment(ctypes.Structure):
@@ -123,9 +124,9 @@ def lib():
         L.hqc_shutdown.argtypes = []
         L.hqc_autotune_decrypt.argtypes = [ctypes.c_int, sz, ctypes.c_int, vp,
                                            ctypes.POINTER(TuneReport)]
-        L.hqc_tune_set.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int]
+        L.hqc_tune_set.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.hqc_tune_get.argtypes = [ctypes.c_int, sz, ctypes.POINTER(ctypes.c_int),
-                                   ctypes.POINTER(ctypes.c_int)]
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.hqc_tune_clear.restype = None
         L.hqc_tune_clear.argtypes = []
         L.hqc_debug_bytes.restype = ctypes.c_size_t
@@ -156,8 +157,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _params(pid, flags, grid, stream, tile=0):
-    return Params(pid, flags, _stream(stream), grid, tile)
+def _params(pid, flags, grid, stream, tile=0, shape=0):
+    return Params(pid, flags, _stream(stream), grid, tile, shape)
 
 
 def _dev(t, dtype, name, shape=None):
@@ -178,12 +179,12 @@ def _out(out, count, k, device):
     return out
 
 
-def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None, tile=0):
+def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None, tile=0, shape=0):
     """m[i] = HQC.PKE.Decrypt(y[i], (u[i], v[i])) for every row (Alg. 2)."""
     s = sizes(pid)
     count = u.shape[0]
     out = _out(out, count, s["k"], u.device)
-    p = _params(pid, flags, grid, stream, tile)
+    p = _params(pid, flags, grid, stream, tile, shape)
     rc = lib().hqc_decrypt_batch(
         ctypes.byref(p), _dev(u, torch.int64, "u", (count, s["u_words"])),
         _dev(v, torch.int64, "v", (count, s["v_words"])),
@@ -193,12 +194,12 @@ def decrypt_batch(pid, u, v, y, out=None, flags=0, grid=0, stream=None, tile=0):
     return out
 
 
-def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None, tile=0):
+def decode_batch(pid, r, out=None, flags=0, grid=0, stream=None, tile=0, shape=0):
     """m[i] = C.Decode(r[i]) (the concatenated decoder alone)."""
     s = sizes(pid)
     count = r.shape[0]
     out = _out(out, count, s["k"], r.device)
-    p = _params(pid, flags, grid, stream, tile)
+    p = _params(pid, flags, grid, stream, tile, shape)
     rc = lib().hqc_decode_batch(ctypes.byref(p), _dev(r, torch.int64, "r", (count, s["v_words"])),
                                 _dev(out, torch.uint8, "out", (count, s["k"])), count)
     _check(rc, "hqc_decode_batch")
@@ -286,12 +287,12 @@ class KeyStore:
             pass
 
 
-def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, stream=None, tile=0):
+def decrypt_batch_keyed(pid, ks, u, v, key_ids, out=None, flags=0, grid=0, stream=None, tile=0, shape=0):
     """decrypt_batch with y[i] = slot key_ids[i] of the keystore."""
     s = sizes(pid)
     count = u.shape[0]
     out = _out(out, count, s["k"], u.device)
-    p = _params(pid, flags, grid, stream, tile)
+    p = _params(pid, flags, grid, stream, tile, shape)
     rc = lib().hqc_decrypt_batch_keyed(
         ctypes.byref(p), ks.handle, _dev(u, torch.int64, "u", (count, s["u_words"])),
         _dev(v, torch.int64, "v", (count, s["v_words"])),
@@ -530,14 +531,18 @@ def autotune_decrypt(pid, count, reps=5, stream=None):
     return {f: getattr(r, f) for f, _ in TuneReport._fields_}
 
 
-def tune_set(pid, count, tile, grid):
-    _check(lib().hqc_tune_set(pid, count, tile, grid), "hqc_tune_set")
+def tune_set(pid, count, tile, grid, shape=1):
+    """Table entry for count's bucket: tile, grid, shape (1 = A, 2 = B);
+    tile = grid = shape = 0 removes it."""
+    _check(lib().hqc_tune_set(pid, count, tile, grid, shape), "hqc_tune_set")
 
 
 def tune_get(pid, count):
-    t, g = ctypes.c_int(), ctypes.c_int()
-    _check(lib().hqc_tune_get(pid, count, ctypes.byref(t), ctypes.byref(g)), "hqc_tune_get")
-    return t.value, g.value
+    """(tile, grid, shape) of count's bucket, or (0, 0, 0)."""
+    t, g, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().hqc_tune_get(pid, count, ctypes.byref(t), ctypes.byref(g), ctypes.byref(sh)),
+           "hqc_tune_get")
+    return t.value, g.value, sh.value
 
 
 def tune_clear():

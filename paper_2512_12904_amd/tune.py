@@ -41,8 +41,9 @@ def tune(sets=(1, 3, 5), counts=DEFAULT_COUNTS, reps=5, stream=None):
 def to_json(reports, arch):
     return {"arch": arch, "entries": [
         {"param_id": r["param_id"], "count": r["count"], "tile": r["tile"], "grid": r["grid"],
-         "ms": r["ms"], "heuristic_tile": r["heuristic_tile"],
-         "heuristic_grid": r["heuristic_grid"], "heuristic_ms": r["heuristic_ms"],
+         "shape": r["shape"], "ms": r["ms"], "heuristic_tile": r["heuristic_tile"],
+         "heuristic_grid": r["heuristic_grid"], "heuristic_shape": r["heuristic_shape"],
+         "heuristic_ms": r["heuristic_ms"],
          "candidates": r["candidates"], "identical": r["identical"]} for r in reports]}
 
 
@@ -67,10 +68,10 @@ def apply(doc, arch):
     for e in doc.get("entries", []):
         if not e.get("identical"):
             continue
-        tile, grid = int(e["tile"]), int(e["grid"])
-        if not (1 <= tile <= 64 and grid >= 1):
+        tile, grid, shape = int(e["tile"]), int(e["grid"]), int(e.get("shape", 1))
+        if not (1 <= tile <= 64 and grid >= 1 and shape in (1, 2)):
             continue
-        hqc.tune_set(int(e["param_id"]), int(e["count"]), tile, grid)
+        hqc.tune_set(int(e["param_id"]), int(e["count"]), tile, grid, shape)
         n += 1
     return n
 

@@ -63,7 +63,8 @@ def test_invalid_arguments_rejected_before_launch(gpu_lib):
     assert L.hqc_decrypt_batch(ctypes.byref(p), vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
     # unknown flag, conflicting flags, tile out of range, negative grid
     for bad in (P(1, 0x100, None, 0, 0), P(1, 3, None, 0, 0), P(1, 0, None, 0, 65),
-                P(1, 0, None, 0, -1), P(1, 0, None, -1, 0)):
+                P(1, 0, None, 0, -1), P(1, 0, None, -1, 0), P(1, 0, None, 0, 0, 3),
+                P(1, 0, None, 0, 0, -1)):
         assert L.hqc_decrypt_batch(ctypes.byref(bad), vp(8), vp(8), vp(8), vp(8), 1) == gpu_lib.HQC_EINVAL
     p = P(1, 0, None, 0, 0)
     # NULL buffers with count > 0

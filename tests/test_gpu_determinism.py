@@ -1,7 +1,7 @@
 """Determinism of the decryption launch: repeated launches give identical
 messages, a permuted batch gives the permuted messages, and every launch
-configuration (tile, grid, graph or direct, tuned table entry) gives the
-same bytes.  Honest ciphertexts and uniformly random words (decoder
+configuration (kernel shape, tile, grid, graph or direct, tuned table
+entry) gives the same bytes.  Honest ciphertexts and uniformly random words (decoder
 failure, where the output is fixed only by the conventions) are mixed."""
 import numpy as np
 import pytest
@@ -50,13 +50,16 @@ def test_repeat_permute_and_configurations(hqc, pid):
     pt = torch.from_numpy(perm).cuda()
     got = hqc.decrypt_batch(pid, du[pt].contiguous(), dv[pt].contiguous(), dy[pt].contiguous())
     assert np.array_equal(got.cpu().numpy(), ref[perm])
-    for tile, grid, flags in [(1, 0, 0), (5, 37, 0), (32, 0, hqc.F_GRAPH), (33, 0, 0), (64, 11, 0),
-                              (0, 3, hqc.F_GRAPH)]:
-        got = hqc.decrypt_batch(pid, du, dv, dy, tile=tile, grid=grid, flags=flags)
-        assert np.array_equal(got.cpu().numpy(), ref), (tile, grid, flags)
+    shapes = (1, 2) if pid != 5 else (1,)
+    for shape in shapes:
+        for tile, grid, flags in [(1, 0, 0), (5, 37, 0), (32, 0, hqc.F_GRAPH), (33, 0, 0),
+                                  (64, 11, 0), (0, 3, hqc.F_GRAPH)]:
+            got = hqc.decrypt_batch(pid, du, dv, dy, tile=tile, grid=grid, flags=flags, shape=shape)
+            assert np.array_equal(got.cpu().numpy(), ref), (tile, grid, flags, shape)
     hqc.tune_clear()
-    hqc.tune_set(pid, count, 16, 50)  # a table entry for this batch size
     try:
-        assert np.array_equal(hqc.decrypt_batch(pid, du, dv, dy).cpu().numpy(), ref)
+        for shape in shapes:
+            hqc.tune_set(pid, count, 16, 50, shape)  # a table entry for this batch size
+            assert np.array_equal(hqc.decrypt_batch(pid, du, dv, dy).cpu().numpy(), ref), shape
     finally:
         hqc.tune_clear()

@@ -365,3 +365,49 @@ def test_keyed_kernels_beyond_radius_match_oracle(hqc, tile):
         torch.cuda.synchronize()
     finally:
         ks.close()
+
+
+@pytest.mark.parametrize("pid", [1, 3])
+@pytest.mark.parametrize("tile", [0, 1, 31, 32, 33, 64])
+def test_shape_b_kernels_match_oracle(hqc, pid, tile):
+    """The second kernel shape (RM blocks on lane pairs, smaller LDS, three
+    wavefronts per SIMD; separate kernel instances for decryption, decoding
+    and keyed decryption): honest ciphertexts (ground truth), random
+    ciphertexts with arbitrary keys and the structured edge words (oracle),
+    over tile sizes with a ragged last tile, every byte compared."""
+    say("case: shape B pid=%d tile=%d" % (pid, tile))
+    p = datasets.sizes(pid)
+    d = datasets.pke(pid, 70, 0x800 + pid)
+    got = host(hqc.decrypt_batch(pid, dev(d["u"]), dev(d["v"]), dev(d["y"]), grid=3, tile=tile,
+                                 shape=2))
+    assert (got == d["m"]).all()
+    u, v, y = _random_inputs(pid)
+    got = host(hqc.decrypt_batch(pid, dev(u), dev(v), dev(y), grid=5, tile=tile, shape=2))
+    assert (got == oracle.decrypt_batch(pid, y, u, v)).all()
+    r = _structured_words(pid)
+    got = host(hqc.decode_batch(pid, dev(r), grid=2, tile=tile, shape=2))
+    assert (got == oracle.decode_batch(pid, r)).all()
+    st = datasets.stress(pid, 50, 0x810 + pid)
+    assert (host(hqc.decode_batch(pid, dev(st["r"]), tile=tile, shape=2)) == st["m"]).all()
+    ks = hqc.KeyStore(70 if pid == 1 else 1, 70 if pid == 3 else 1, 1)
+    try:
+        ks.put(pid, 0, d["y_keys"])
+        import torch
+        ids = torch.arange(70, dtype=torch.int32, device="cuda")
+        got = host(hqc.decrypt_batch_keyed(pid, ks, dev(d["u"]), dev(d["v"]), ids, tile=tile,
+                                           shape=2))
+        assert (got == d["m"]).all()
+    finally:
+        ks.close()
+
+
+def test_shape_argument_checks(hqc):
+    """Shape B exists for single-set HQC-1 / HQC-3 launches only."""
+    say("case: shape argument checks")
+    d = datasets.pke(5, 4, 0x820)
+    with pytest.raises(hqc.HqcError):
+        hqc.decrypt_batch(5, dev(d["u"]), dev(d["v"]), dev(d["y"]), shape=2)
+    with pytest.raises(hqc.HqcError):
+        hqc.decrypt_batch(5, dev(d["u"]), dev(d["v"]), dev(d["y"]), shape=3)
+    # shape A explicitly: the same messages
+    assert (host(hqc.decrypt_batch(5, dev(d["u"]), dev(d["v"]), dev(d["y"]), shape=1)) == d["m"]).all()

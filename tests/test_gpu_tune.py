@@ -21,8 +21,9 @@ def test_autotune_then_default_launch_matches_checker(pid):
     r = hqc.autotune_decrypt(pid, count, reps=2)
     assert r["identical"] == 1 and r["count"] == count and r["candidates"] >= 1
     assert 1 <= r["tile"] <= 64 and r["grid"] >= 1
+    assert r["shape"] in ((1, 2) if pid != 5 else (1,)) and r["heuristic_shape"] in (1, 2)
     assert r["ms"] <= r["heuristic_ms"] + 1e-6
-    assert hqc.tune_get(pid, count) == (r["tile"], r["grid"])
+    assert hqc.tune_get(pid, count) == (r["tile"], r["grid"], r["shape"])
     d = datasets.pke(pid, count, 0x7A0 + pid)
     dev = "cuda"
     u = torch.from_numpy(d["u"].view(np.int64)).to(dev)
