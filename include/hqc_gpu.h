@@ -332,7 +332,8 @@ void hqc_shutdown(void);
  * configuration to use when a single-set call leaves params->grid,
  * params->tile and params->shape at 0; without an entry it uses shape A
  * (shape B for HQC-1 once count fills B's occupancy grid with tiles of 32),
- * the occupancy grid and tile = ceil(count / grid), at most 64.  Because the
+ * the occupancy grid and tile = ceil(count / grid), at most 64 (32 for HQC-1
+ * decryption).  Because the
  * kernels' time does not depend on the data (constant time), configurations
  * can be timed on random inputs. */
 typedef struct hqc_tune_report {

@@ -234,9 +234,13 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
   }
   if (grid <= 0) grid = full;
   if (tile == 0) {
-    // enough tiles to give every resident workgroup one, at most 64 items each
+    // enough tiles to give every resident workgroup one, at most 64 items
+    // each -- at most 32 for HQC-1 decryption, whose lane-pair Reed-Solomon
+    // form (tiles of up to 32) measured faster than the one-lane form there
+    // (131,072 items: 0.65 vs 0.73 ms); decoding keeps the larger tiles
+    const uint64_t cap = (mask == 1u && op != hqc::OP_DECODE) ? 32 : 64;
     uint64_t per = (items + (uint64_t)grid - 1) / (uint64_t)grid;
-    tile = (uint32_t)(per < 1 ? 1 : per > 64 ? 64 : per);
+    tile = (uint32_t)(per < 1 ? 1 : per > cap ? cap : per);
   }
   assign_tiles(a, tile);
   if ((uint32_t)grid > a.total) grid = (int)a.total;

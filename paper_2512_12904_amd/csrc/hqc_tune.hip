@@ -97,7 +97,9 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
   // occupancy grid and enough tiles for it)
   const int h_shape = (mask == 1u && nshape == 2 && count >= 32 * (size_t)full[1]) ? 1 : 0;
   const int h_full = full[h_shape];
-  const int h_tile = (int)std::min<size_t>(64, std::max<size_t>(1, (count + h_full - 1) / h_full));
+  const size_t h_cap = mask == 1u ? 32 : 64;  // as the library's built-in choice
+  const int h_tile =
+      (int)std::min<size_t>(h_cap, std::max<size_t>(1, (count + h_full - 1) / h_full));
   struct Cand {
     int shape, tile, grid;
     bool operator==(const Cand &o) const {

@@ -94,13 +94,17 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="JSON path (default: the per-arch cache file)")
     a = ap.parse_args(argv)
-    reports = tune([int(x) for x in a.sets.split(",")], [int(x) for x in a.counts.split(",")],
-                   a.reps)
+    reports = []
+    for pid in (int(x) for x in a.sets.split(",")):
+        # one set at a time, so that progress shows as it goes
+        reports += tune([pid], [int(x) for x in a.counts.split(",")], a.reps)
+        print("HQC-%d tuned" % pid, flush=True)
     for r in reports:
-        print("HQC-%d count %7d: tile %2d grid %5d %.4f ms (default tile %2d grid %5d %.4f ms, "
-              "%d candidates, identical %d)" % (
-                  r["param_id"], r["count"], r["tile"], r["grid"], r["ms"], r["heuristic_tile"],
-                  r["heuristic_grid"], r["heuristic_ms"], r["candidates"], r["identical"]),
+        print("HQC-%d count %7d: shape %s tile %2d grid %5d %.4f ms (default shape %s tile %2d "
+              "grid %5d %.4f ms, %d candidates, identical %d)" % (
+                  r["param_id"], r["count"], "AB"[r["shape"] - 1], r["tile"], r["grid"], r["ms"],
+                  "AB"[r["heuristic_shape"] - 1], r["heuristic_tile"], r["heuristic_grid"],
+                  r["heuristic_ms"], r["candidates"], r["identical"]),
               flush=True)
     print("saved", save(reports, a.out))
 
