@@ -85,19 +85,22 @@ def make_inputs(pid, count, seed, device):
     u, v = hqc.encrypt_batch(pid, hd, sd, md, r1d, r2d, ed)
     torch.cuda.synchronize()
     # the first calls above loaded the kernels; time reps more of each with
-    # HIP events on the launch stream (same inputs, same outputs)
+    # HIP events on the launch stream (same inputs, same outputs), each after
+    # a pre-warm of the same launch
     reps = 3
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
-    ev[0].record()
-    for i in range(reps):
-        hqc.keygen_batch(pid, hd, xd, yd, out=sd)
-        ev[1 + i].record()
-    for i in range(reps):
-        hqc.encrypt_batch(pid, hd, sd, md, r1d, r2d, ed, u_out=u, v_out=v)
-        ev[1 + reps + i].record()
-    torch.cuda.synchronize()
-    times = {"keygen_ms": sum(ev[i].elapsed_time(ev[i + 1]) for i in range(reps)) / reps,
-             "encrypt_ms": sum(ev[reps + i].elapsed_time(ev[reps + i + 1]) for i in range(reps)) / reps}
+    def timed(launch):
+        prewarm(launch, PREWARM_S / 2)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            launch()
+            ev[1 + i].record()
+        torch.cuda.synchronize()
+        return sum(ev[i].elapsed_time(ev[i + 1]) for i in range(reps)) / reps
+
+    times = {"keygen_ms": timed(lambda: hqc.keygen_batch(pid, hd, xd, yd, out=sd)),
+             "encrypt_ms": timed(lambda: hqc.encrypt_batch(pid, hd, sd, md, r1d, r2d, ed,
+                                                           u_out=u, v_out=v))}
     del hd, xd, sd, r1d, r2d, ed
     return u, v, yd, md, times
 
@@ -120,17 +123,20 @@ def kem_bench(hqc, pid, count, seed, device, reps=3):
     u, v, key = hqc.kem_encaps_batch(pid, hd, sd, md, workspace=ws)
     key2 = hqc.kem_decaps_batch(pid, hd, sd, yd, sg, u, v, workspace=ws)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
-    ev[0].record()
-    for i in range(reps):
-        hqc.kem_encaps_batch(pid, hd, sd, md, u_out=u, v_out=v, key_out=key, workspace=ws)
-        ev[1 + i].record()
-    for i in range(reps):
-        hqc.kem_decaps_batch(pid, hd, sd, yd, sg, u, v, key_out=key2, workspace=ws)
-        ev[1 + reps + i].record()
-    torch.cuda.synchronize()
-    enc = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-    dec = [ev[reps + i].elapsed_time(ev[reps + i + 1]) for i in range(reps)]
+    def timed(launch):
+        prewarm(launch, PREWARM_S / 2)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            launch()
+            ev[1 + i].record()
+        torch.cuda.synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+    enc = timed(lambda: hqc.kem_encaps_batch(pid, hd, sd, md, u_out=u, v_out=v, key_out=key,
+                                             workspace=ws))
+    dec = timed(lambda: hqc.kem_decaps_batch(pid, hd, sd, yd, sg, u, v, key_out=key2,
+                                             workspace=ws))
     r = {"kem_encaps_ms": sum(enc) / reps, "kem_decaps_ms": sum(dec) / reps,
          "kem_encaps_per_s": count / (sum(enc) / reps / 1e3),
          "kem_decaps_per_s": count / (sum(dec) / reps / 1e3),
@@ -202,19 +208,38 @@ def ct_classes(hqc, pid, count, device, reps=3):
     return {"class_a_launches": reps, "class_b_launches": reps, "items": count}
 
 
+# Untimed launches of the same step, for this long, before the warm-up steps:
+# after the host-side input generation the GPU has idled and its clocks ramp
+# back up over the first ~25 launches (measured 0.39 -> 0.365 ms per HQC-1
+# launch), so the timed launches run at the sustained clock of continuous load.
+PREWARM_S = 0.2
+
+
+def prewarm(launch, seconds=PREWARM_S):
+    """Repeat launch() (synchronising every few calls) for about `seconds`."""
+    import torch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            launch()
+        torch.cuda.synchronize()
+
+
 def time_batched(hqc, pid, u, v, y, out, steps, warmup):
     """Per-launch device times (ms) from HIP events on the launch stream."""
     import torch
     stream = torch.cuda.current_stream()
+    prewarm(lambda: hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream,
+                                      grid=GRID, tile=TILE, shape=shape_for(pid)))
     for _ in range(warmup):
-        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE)
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE, shape=shape_for(pid))
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
-        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE)
+        hqc.decrypt_batch(pid, u, v, y, out=out, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE, shape=shape_for(pid))
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -239,7 +264,7 @@ def time_end_to_end(hqc, pid, u, v, y, m, reps=3):
         du.copy_(hu, non_blocking=True)
         dv.copy_(hv, non_blocking=True)
         dy.copy_(hy, non_blocking=True)
-        hqc.decrypt_batch(pid, du, dv, dy, out=dm, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE)
+        hqc.decrypt_batch(pid, du, dv, dy, out=dm, flags=hqc.F_GRAPH, stream=stream, grid=GRID, tile=TILE, shape=shape_for(pid))
         hm.copy_(dm, non_blocking=True)
 
     one()
@@ -267,6 +292,12 @@ def time_per_item(hqc, pid, u, v, y, out):
 
 GRID = 0  # launch knobs (0 = the library's choice); set from the command line
 TILE = 0
+SHAPE = 0
+
+
+def shape_for(pid):
+    """The --shape knob where the set has that shape (shape B: HQC-1, HQC-3)."""
+    return SHAPE if (SHAPE < 2 or pid != 5) else 0
 
 # the sources the decryption kernel is compiled from
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12904_amd", "csrc", f)
@@ -282,12 +313,14 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def committed_counters(name):
+def committed_counters(name, launch=None):
     """The committed rocprofv3 counter summary of one decryption kernel
     (name: "HQC-1", "HQC-3", "HQC-5" at 65,536 items, or "decode_mixed" at
     1,048,576 words): VALU busy, instructions per item and HBM bytes per
     launch (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's counts) --
-    if they were taken on the kernel source as it is now; else None."""
+    if they were taken on the kernel source as it is now and, when `launch`
+    (dict of shape, tile, grid) is given, in that launch configuration;
+    else None."""
     try:
         with open(COUNTERS_FILE) as f:
             t = json.load(f)
@@ -295,7 +328,21 @@ def committed_counters(name):
         return None
     if t.get("kernel_source_sha256") != kernel_sha():
         return None
-    return t.get("kernels", {}).get(name)
+    e = t.get("kernels", {}).get(name)
+    if e is not None and launch is not None and e.get("launch") != launch:
+        return None
+    return e
+
+
+def timed_launch(pid, tuned):
+    """(shape, tile, grid) of the timed launches of a set, when known: the
+    autotuner's entry, or the configuration given on the command line."""
+    if pid in tuned:
+        t = tuned[pid]
+        return {"shape": t["shape"], "tile": t["tile"], "grid": t["grid"]}
+    if GRID and TILE and shape_for(pid):
+        return {"shape": shape_for(pid), "tile": TILE, "grid": GRID}
+    return None
 
 
 def copy_calibration(mib, device):
@@ -384,6 +431,7 @@ def time_decode_mixed(hqc, items, msgs, reps):
     ok = all(bool(torch.equal(o, m)) for o, m in zip(outs, msgs))
     for it, o in zip(items, outs):
         it["out"] = o
+    prewarm(lambda: hqc.decode_mixed(items, flags=hqc.F_GRAPH, stream=stream))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record(stream)
     for i in range(reps):
@@ -645,6 +693,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--tile", type=int, default=0, help="items per workgroup (0 = library)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups (0 = library)")
+    ap.add_argument("--shape", type=int, default=0, choices=(0, 1, 2),
+                    help="kernel shape: 0 = library, 1 = A, 2 = B (sets that have it)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's built-in launch configuration instead of running "
                          "the autotuner for each set and batch size first")
@@ -659,8 +709,8 @@ def main():
     import torch
     from paper_2512_12904_amd import hqc
 
-    global GRID, TILE
-    GRID, TILE = args.grid, args.tile
+    global GRID, TILE, SHAPE
+    GRID, TILE, SHAPE = args.grid, args.tile, args.shape
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hqc.lib()
@@ -679,7 +729,7 @@ def main():
     results = {}
     tuned = {}
     for pid in sets:
-        if not args.no_autotune and GRID == 0 and TILE == 0:
+        if not args.no_autotune and GRID == 0 and TILE == 0 and SHAPE == 0:
             # the library's autotuner picks (tile, grid) for this set and batch size
             tuned[pid] = hqc.autotune_decrypt(pid, args.count, reps=5)
         u, v, y, m, gen = make_inputs(pid, args.count, 0xBE00 + pid, dev)
@@ -712,7 +762,8 @@ def main():
             u = v = y = m = out = None
             r.update(kem_bench(hqc, pid, args.count, 0xC0DE + pid, dev))
         r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
-        cc = committed_counters("HQC-%d" % pid) if args.count == 65536 else None
+        tl = timed_launch(pid, tuned)
+        cc = committed_counters("HQC-%d" % pid, tl) if (args.count == 65536 and tl) else None
         if cc:
             # issue-slot fraction of the VALU from the committed counters of
             # this kernel source, beside the op-model fraction
@@ -757,7 +808,8 @@ def main():
                    "launch": "hipGraph, persistent grid, %s" % (
                        "shape %s, tile %d x grid %d from the autotuner" % (
                            "AB"[tuned[pid0]["shape"] - 1], tuned[pid0]["tile"], tuned[pid0]["grid"])
-                       if pid0 in tuned else "tile %d / grid %d (0 = library default)" % (TILE, GRID))},
+                       if pid0 in tuned else "shape %d / tile %d / grid %d (0 = library default)"
+                       % (shape_for(pid0), TILE, GRID))},
         "gpu": gpu_info(dev),
         "p50_launch_ms": main_r["ms_p50"],
         "p99_launch_ms": main_r["ms_p99"],
@@ -765,8 +817,9 @@ def main():
                                    for kk, vv in r.items()} for k, r in results.items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS,
-                     "traffic": ((committed_counters("HQC-%d" % pid0) or {}).get("traffic_bytes")
-                                 if args.count == 65536 else None),
+                     "traffic": ((committed_counters("HQC-%d" % pid0, timed_launch(pid0, tuned))
+                                  or {}).get("traffic_bytes")
+                                 if (args.count == 65536 and timed_launch(pid0, tuned)) else None),
                      "traffic_algorithmic": hbm_bytes(pid0) * args.count,
                      "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
                      "kernel_ms": main_r["ms_mean"]},
