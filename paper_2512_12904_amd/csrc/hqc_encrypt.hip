@@ -232,7 +232,7 @@ __device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
 }
 
 // acc = the lane's R dwords of a * (sum over the support of X^index)
-template <int ID, int N>
+template <int ID, int N, bool PIPE = false>
 __device__ __forceinline__ void sparse_product(const uint32_t *u2,
                                                const uint32_t (&idx)[(N + 63) / 64],
                                                uint32_t (&acc)[Geo<ID>::R]) {
@@ -240,7 +240,8 @@ __device__ __forceinline__ void sparse_product(const uint32_t *u2,
   window_shifts<ID, (N + 63) / 64>(idx, sh);
 #pragma unroll
   for (int j = 0; j < Geo<ID>::R; ++j) acc[j] = 0;
-  product_acc<ID, N>(u2, sh, acc);
+  if constexpr (PIPE) product_acc_pipelined<ID, N>(u2, sh, acc);
+  else product_acc<ID, N>(u2, sh, acc);
 }
 
 // acc ^= the lane's R dwords of sum over the support of X^(index mod n),
@@ -350,7 +351,11 @@ __device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
 
 // Per-set shape of the encryption kernels, chosen by timing: waves per SIMD
 // (the register budget; sampled_waves for the kernels that sample the
-// supports from draws: encapsulation and the re-encryption check), whether
+// supports from draws: encapsulation and the re-encryption check;
+// keygen_waves for key generation, whose product h*y loads the next group
+// of windows while the current one is combined when keygen_pipelined --
+// HQC-3 and HQC-5, 6 % faster; encryption keeps two rows live and has no
+// registers for a second set of windows), whether
 // h and s are loaded an item ahead in encryption (pipe; two more rows of
 // registers) and h in key generation (keygen_pipe), whether the check
 // loads the received u and v before the products that precede their
@@ -360,15 +365,18 @@ __device__ __forceinline__ uint32_t compare_row(const uint32_t *buf, int ndw,
 // the LDS staging buffer (one single-lane atomic XOR each).
 template <int ID> struct EncShape;
 template <> struct EncShape<1> {
-  static constexpr int waves = 4, sampled_waves = 5;
+  static constexpr int waves = 4, sampled_waves = 5, keygen_waves = 4;
+  static constexpr bool keygen_pipelined = false;
   static constexpr bool pipe = true, keygen_pipe = false, check_ahead = true, reg_xor = true;
 };
 template <> struct EncShape<3> {
-  static constexpr int waves = 4, sampled_waves = 4;
+  static constexpr int waves = 4, sampled_waves = 4, keygen_waves = 3;
+  static constexpr bool keygen_pipelined = true;
   static constexpr bool pipe = true, keygen_pipe = true, check_ahead = false, reg_xor = false;
 };
 template <> struct EncShape<5> {
-  static constexpr int waves = 1, sampled_waves = 1;
+  static constexpr int waves = 1, sampled_waves = 1, keygen_waves = 2;
+  static constexpr bool keygen_pipelined = true;
   static constexpr bool pipe = true, keygen_pipe = true, check_ahead = true, reg_xor = false;
 };
 
@@ -447,7 +455,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     build_doubled_regs<ID, kDenseRegs<ID>>(u2, hr);
     wave_sync();
     if (KPIPE && next < a.count) load_dense<ID>(a.h + (size_t)next * nw, hr);
-    sparse_product<ID, G::w>(u2, iy, acc);
+    sparse_product<ID, G::w, EncShape<ID>::keygen_pipelined>(u2, iy, acc);
     if constexpr (REG_XOR) sparse_xor<ID, G::w>(acc, ix, (uint32_t)G::n);
     wave_sync();  // every window of U2 has been read
     put_full<ID>(buf, acc);
@@ -550,6 +558,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
 
 template <int MODE, int ID>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == ENC_STREAM || MODE == ENC_CHECK ? EncShape<ID>::sampled_waves
+                                   : MODE == ENC_KEYGEN                     ? EncShape<ID>::keygen_waves
                                                                             : EncShape<ID>::waves))) void
 hqc_encrypt_kernel(EncArgs a) {
   extern __shared__ uint32_t lds[];

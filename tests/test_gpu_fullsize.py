@@ -41,14 +41,20 @@ def dev(a):
     return torch.from_numpy(a).cuda()
 
 
-@pytest.mark.parametrize("pid,master", [(1, 0x2), (3, 0x3), (5, 0x5)])
-def test_decrypt_65536_one_launch(hqc, pid, master):
+# launch configurations: the library's default, and the one the autotuner
+# picks for HQC-1 at this size on MI355X (shape B, tiles of 16, 3,072
+# workgroups), which bench.py times
+@pytest.mark.parametrize("pid,master,launch", [(1, 0x2, None), (1, 0x2, (2, 16, 3072)),
+                                               (3, 0x3, None), (5, 0x5, None)])
+def test_decrypt_65536_one_launch(hqc, pid, master, launch):
     import torch
     count = 65536
-    print("case: full-size decrypt pid=%d count=%d" % (pid, count), flush=True)
+    print("case: full-size decrypt pid=%d count=%d launch=%s" % (pid, count, launch), flush=True)
     d = datasets.pke(pid, count, master)
     print("  generated", flush=True)
-    out = hqc.decrypt_batch(pid, dev(d["u"]), dev(d["v"]), dev(d["y"]), flags=hqc.F_GRAPH)
+    shape, tile, grid = launch or (0, 0, 0)
+    out = hqc.decrypt_batch(pid, dev(d["u"]), dev(d["v"]), dev(d["y"]), flags=hqc.F_GRAPH,
+                            shape=shape, tile=tile, grid=grid)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     bad = np.flatnonzero((got != d["m"]).any(1))
