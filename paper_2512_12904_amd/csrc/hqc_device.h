@@ -77,6 +77,42 @@ template <int ID, int SH = 0> struct Geo {
   static_assert(LDS_BYTES * 4 * WAVES <= 160 * 1024, "LDS of the wavefronts per CU");
 };
 
+// ---- LDS and row index expressions -----------------------------------------
+// The index arithmetic of the kernels' LDS and row accesses, for geometry G.
+// The kernels compute their addresses with these functions, and a host-side
+// check (tests) evaluates the same functions over every lane, shift, tile
+// row and pass against the LDS and buffer sizes.  Offsets are in dwords
+// from the start of the dynamic LDS, except the symbol tables (bytes).
+template <class G> struct Layout {
+  static constexpr int BPP = G::PAIR_RM ? 32 : 64;  // RM blocks per pass
+  // decryption: received-word slot q starts at rb(q); dword d of a word sits
+  // at rb(q) + row(d) (one RM block per padded row of BSTR dwords)
+  static __host__ __device__ constexpr int rb(int q) { return G::RB_OFF + q * G::RB; }
+  static __host__ __device__ constexpr int row(int d) { return d + d / G::BLK; }
+  // first dword of block b of slot q
+  static __host__ __device__ constexpr int block(int q, int b) { return rb(q) + b * G::BSTR; }
+  // dword j (0 .. R) of lane l's product window for the shift sh (doubled copy)
+  static __host__ __device__ constexpr int window(int lane, uint32_t sh, int j) {
+    return lane * G::R + (int)(sh >> 5) + j;
+  }
+  // output dword j (0 .. R - 1) of lane l's product
+  static __host__ __device__ constexpr int out(int lane, int j) { return lane * G::R + j; }
+  // decryption: byte b of row r of the tile's symbol table
+  static __host__ __device__ constexpr int sym(int r, int b) { return G::A_BYTES + r * G::SSTR + b; }
+  // RM pass p of a group: the flat block index lane takes (q n1 + b for
+  // block b of slot q), before clamping to the blocks received
+  static __host__ __device__ constexpr int pass_flat(int p, int lane) {
+    return BPP * p + (G::PAIR_RM ? (lane & 31) : lane);
+  }
+  static __host__ __device__ constexpr int pass_clamp(int fl, int avail) {
+    return fl < avail ? fl : avail - 1;
+  }
+  // key generation / encryption: byte b of the symbol table after the
+  // doubled copy (the output staging buffer starts at dword 0)
+  static __host__ __device__ constexpr int enc_sym(int b) { return 4 * G::U2 + b; }
+  static constexpr int ENC_LDS_BYTES = 4 * G::U2 + (G::n1 + 63) / 64 * 64;
+};
+
 // ---- GF(2^8) tables, x^8 + x^4 + x^3 + x^2 + 1, alpha = x ------------------
 // A 256-byte table is held in lanes 0 .. 31, 8 bytes per lane (lo: bytes
 // 8l .. 8l+3, hi: 8l+4 .. 8l+7; lanes 32 .. 63 hold a copy).  A lookup
@@ -275,7 +311,8 @@ __device__ __forceinline__ void product_acc(const uint32_t *u2,
                                             uint32_t (&acc)[Geo<ID>::R]) {
   using G = Geo<ID>;
   constexpr int NREG = (NIDX + 63) / 64;
-  const uint32_t *base = u2 + lane_id() * G::R;
+  using L = Layout<G>;
+  const int lane = lane_id();
   constexpr int U = G::R <= 10 ? 4 : 2;
 #pragma unroll
   for (int c = 0; c < NREG; ++c) {
@@ -287,7 +324,7 @@ __device__ __forceinline__ void product_acc(const uint32_t *u2,
       for (int q = 0; q < U; ++q) {
         shs[q] = rdlane(shreg[c], kk + q);
 #pragma unroll
-        for (int j = 0; j <= G::R; ++j) win[q][j] = base[(shs[q] >> 5) + j];
+        for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
       }
 #pragma unroll
       for (int q = 0; q < U; q += 2)
@@ -300,7 +337,7 @@ __device__ __forceinline__ void product_acc(const uint32_t *u2,
       uint32_t win[G::R + 1];
       const uint32_t sh = rdlane(shreg[c], kk);
 #pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[j] = base[(sh >> 5) + j];
+      for (int j = 0; j <= G::R; ++j) win[j] = u2[L::window(lane, sh, j)];
 #pragma unroll
       for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
     }
@@ -316,14 +353,15 @@ __device__ __forceinline__ void product_acc_pipelined(const uint32_t *u2,
                                                       uint32_t (&acc)[Geo<ID>::R]) {
   using G = Geo<ID>;
   constexpr int NREG = (NIDX + 63) / 64;
-  const uint32_t *base = u2 + lane_id() * G::R;
+  using L = Layout<G>;
+  const int lane = lane_id();
   constexpr int U = G::R <= 10 ? 4 : 2;
   auto load = [&](uint32_t (&win)[U][G::R + 1], uint32_t (&shs)[U], int c, int k0) {
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       shs[q] = rdlane(shreg[c], k0 + q);
 #pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[q][j] = base[(shs[q] >> 5) + j];
+      for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
     }
   };
   auto combine = [&](const uint32_t (&win)[U][G::R + 1], const uint32_t (&shs)[U]) {
@@ -355,7 +393,7 @@ __device__ __forceinline__ void product_acc_pipelined(const uint32_t *u2,
       uint32_t win[G::R + 1];
       const uint32_t sh = rdlane(shreg[c], kk);
 #pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[j] = base[(sh >> 5) + j];
+      for (int j = 0; j <= G::R; ++j) win[j] = u2[L::window(lane, sh, j)];
 #pragma unroll
       for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
     }

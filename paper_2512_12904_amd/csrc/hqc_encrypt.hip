@@ -311,7 +311,7 @@ __device__ __forceinline__ void put_full(uint32_t *buf, const uint32_t (&acc)[Ge
   const int lane = lane_id();
 #pragma unroll
   for (int j = 0; j < G::R; ++j) {
-    const int d = lane * G::R + j;
+    const int d = Layout<G>::out(lane, j);
     if (d <= G::DW) buf[d] = d < G::DW ? acc[j] : acc[j] & ((1u << G::NB) - 1u);
   }
 }
@@ -390,7 +390,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
   // product has read it (a wave_sync orders the two)
   uint32_t *u2 = lds;
   uint32_t *buf = lds;
-  uint8_t *sym = (uint8_t *)(lds + G::U2);
+  uint8_t *sym = (uint8_t *)lds + Layout<G>::enc_sym(0);
   uint32_t acc[G::R];
   constexpr bool REG_XOR = EncShape<ID>::reg_xor;
   const size_t nw = (size_t)G::U_WORDS;
@@ -535,7 +535,7 @@ __device__ __forceinline__ void run_item(const EncArgs &a, uint32_t item, uint32
     asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
-      const int d = ln * G::R + j;
+      const int d = Layout<G>::out(ln, j);
       const int dd = d < G::W32 ? d : 0;
       const int blk = dd / G::BLK, w = (dd % G::BLK) & 3;
       const uint32_t word = rm_dword(sym[blk], (uint32_t)w, pat);
@@ -574,10 +574,7 @@ hqc_encrypt_kernel(EncArgs a) {
     run_item<ID, MODE>(a, item, item + gridDim.x, lds, pat, hr);
 }
 
-template <int ID> size_t enc_lds() {
-  using G = Geo<ID>;
-  return sizeof(uint32_t) * G::U2 + ((G::n1 + 63) / 64) * 64;
-}
+template <int ID> size_t enc_lds() { return Layout<Geo<ID>>::ENC_LDS_BYTES; }
 
 }  // namespace
 

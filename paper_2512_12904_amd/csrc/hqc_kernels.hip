@@ -306,6 +306,7 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
                                               const uint32_t *vsrc, const SegDev &sg,
                                               uint32_t next_item, bool next) {
   using G = Geo<ID, SH>;
+  using L = Layout<G>;
   using IR = ItemRegs<ID>;
   const int lane = lane_id();
   uint32_t *u2 = lds;
@@ -314,7 +315,7 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
 #pragma unroll
     for (int i = 0; i < IR::VREG; ++i) {
       const int d = lane + 64 * i;
-      if (d < G::W32) rb[d + d / G::BLK] = r.v[i];
+      if (d < G::W32) rb[L::row(d)] = r.v[i];
     }
   }
   if constexpr (OP == OP_DECODE) {
@@ -340,20 +341,20 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
     wave_sync();  // every window of U2 has been read: the rows take its place
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
-      const int d = lane * G::R + j;
-      if (d < G::W32) rb[d + d / G::BLK] = acc[j];
+      const int d = L::out(lane, j);
+      if (d < G::W32) rb[L::row(d)] = acc[j];
     }
     wave_sync();
 #pragma unroll
     for (int i = 0; i < IR::VREG; ++i) {
       const int d = lane + 64 * i;
-      if (d < G::W32) rb[d + d / G::BLK] ^= vsrc[d];
+      if (d < G::W32) rb[L::row(d)] ^= vsrc[d];
     }
   } else {
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
-      const int d = lane * G::R + j;
-      if (d < G::W32) rb[d + d / G::BLK] ^= acc[j];
+      const int d = L::out(lane, j);
+      if (d < G::W32) rb[L::row(d)] ^= acc[j];
     }
   }
 }
@@ -969,8 +970,9 @@ template <int ID, int OP, int SH>
 __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
                                         GfTab exp4, GfTab log4) {
   using G = Geo<ID, SH>;
+  using L = Layout<G>;
   const int lane = lane_id();
-  uint8_t *sym = (uint8_t *)lds + G::A_BYTES;
+  uint8_t *const lds8 = (uint8_t *)lds;
   // the next item's u, v and y are loaded into VGPRs while this one's RM
   // blocks decode (HQC-1: already while its product runs); the compact
   // layout (HQC-5) loads each item when it starts, leaving the latency to
@@ -986,14 +988,14 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
     // product is short: the loads would not be covered by RM passes alone);
     // HQC-3 after it (measured 1 % faster there)
     constexpr bool EARLY = ID == 1;
-    received_word<ID, OP, SH>(regs, lds, lds + G::RB_OFF + gi * G::RB,
+    received_word<ID, OP, SH>(regs, lds, lds + L::rb(gi),
                           (const uint32_t *)(sg.v + (size_t)cur * G::V_WORDS), sg, cur + 1,
                           EARLY && it + 1 < nt);
     wave_sync();
     if (OP == OP_DEBUG && sg.dbg) {  // debug launch: the received word, in item order
-      const uint32_t *rb = lds + G::RB_OFF + gi * G::RB;
+      const uint32_t *rb = lds + L::rb(gi);
       uint32_t *dst = (uint32_t *)(sg.dbg + (size_t)cur * G::DBG_BYTES);
-      for (int d = lane; d < G::W32; d += 64) dst[d] = rb[d + d / G::BLK];
+      for (int d = lane; d < G::W32; d += 64) dst[d] = rb[L::row(d)];
     }
     if (!G::COMPACT && !EARLY && it + 1 < nt) prefetch<ID, OP, SH>(sg, cur + 1, regs);
     {
@@ -1001,22 +1003,22 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
       // decoded BPP at a time (one lane or one lane pair each) as soon as the
       // received words holding them are complete, so that most items' loads
       // overlap a pass
-      constexpr int BPP = G::PAIR_RM ? 32 : 64;
+      constexpr int BPP = L::BPP;
       const int g0 = it - gi, avail = (gi + 1) * G::n1;
       const bool last = gi == G::RMG - 1 || it == nt - 1;
       if (gi == 0) passes = 0;
 #pragma unroll 1
       while (passes * BPP < avail && ((passes + 1) * BPP <= avail || last)) {
-        const int f0 = BPP * passes, fl = f0 + (G::PAIR_RM ? (lane & 31) : lane);
-        const int f = fl < avail ? fl : avail - 1;
+        const int fl = L::pass_flat(passes, lane);
+        const int f = L::pass_clamp(fl, avail);
         const int q = f / G::n1, b = f - q * G::n1;
-        const uint32_t *blk = lds + G::RB_OFF + q * G::RB + b * G::BSTR;
+        const uint32_t *blk = lds + L::block(q, b);
         uint32_t sbyte;
         if constexpr (G::PAIR_RM)
           sbyte = rm_decode_pair<G::MULT>(blk);
         else
           sbyte = rm_decode_block<G::MULT>(blk);
-        if (fl < avail && lane < BPP) sym[(g0 + q) * G::SSTR + b] = (uint8_t)sbyte;
+        if (fl < avail && lane < BPP) lds8[L::sym(g0 + q, b)] = (uint8_t)sbyte;
         ++passes;
       }
       wave_sync();
@@ -1036,12 +1038,12 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   }
   uint8_t *dbg = (OP == OP_DEBUG && sg.dbg && active) ? sg.dbg + (size_t)item * G::DBG_BYTES : nullptr;
   if constexpr (G::COMPACT) {
-    rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
+    rs_pair<ID, OP>(sg, item, active && !bad_key, lds8 + L::sym(slot, 0), exp4, log4, dbg);
   } else {
     if (pair)
-      rs_pair<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
+      rs_pair<ID, OP>(sg, item, active && !bad_key, lds8 + L::sym(slot, 0), exp4, log4, dbg);
     else
-      rs_lane<ID, OP>(sg, item, active && !bad_key, sym + slot * G::SSTR, exp4, log4, dbg);
+      rs_lane<ID, OP>(sg, item, active && !bad_key, lds8 + L::sym(slot, 0), exp4, log4, dbg);
   }
   if constexpr (OP == OP_KEYED) {
     if (active && bad_key && s == lane) {
