@@ -269,7 +269,7 @@ __device__ __forceinline__ void prefetch(const SegDev &sg, uint32_t item, ItemRe
   const int lane = lane_id();
   const uint32_t *vsrc = (const uint32_t *)((OP == OP_DECODE ? sg.u : sg.v) +
                                             (size_t)item * G::V_WORDS);
-  if (!G::COMPACT || OP == OP_DECODE) {  // the compact layout reads v after the product
+  {  // v with u and y (the compact layout keeps it until the product is done)
 #pragma unroll
     for (int i = 0; i < IR::VREG; ++i) {
       const int d = lane + 64 * i;
@@ -348,7 +348,7 @@ __device__ __forceinline__ void received_word(ItemRegs<ID> &r, uint32_t *lds, ui
 #pragma unroll
     for (int i = 0; i < IR::VREG; ++i) {
       const int d = lane + 64 * i;
-      if (d < G::W32) rb[L::row(d)] ^= vsrc[d];
+      if (d < G::W32) rb[L::row(d)] ^= r.v[i];
     }
   } else {
 #pragma unroll
@@ -975,8 +975,9 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
   uint8_t *const lds8 = (uint8_t *)lds;
   // the next item's u, v and y are loaded into VGPRs while this one's RM
   // blocks decode (HQC-1: already while its product runs); the compact
-  // layout (HQC-5) loads each item when it starts, leaving the latency to
-  // the other wavefronts on the SIMD
+  // layout (HQC-5) loads each item's u, v and y together when it starts
+  // (v too, so that its latency passes during the product: HQC-5 -11 %),
+  // leaving the rest of the latency to the other wavefronts on the SIMD
   ItemRegs<ID> regs;
   if constexpr (!G::COMPACT) prefetch<ID, OP, SH>(sg, item0, regs);
   int passes = 0;  // RM passes done for the current group
