@@ -966,9 +966,11 @@ __device__ __forceinline__ void rs_pair(const SegDev &sg, uint32_t item, bool ac
   }
 }
 
+// The RM symbols of nt <= TROWS consecutive items from item0 (S0-S5) into
+// rows row0 .. row0 + nt - 1 of the symbol table.
 template <int ID, int OP, int SH>
-__device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
-                                        GfTab exp4, GfTab log4) {
+__device__ __forceinline__ void symbols(const SegDev &sg, uint32_t item0, int nt, int row0,
+                                        uint32_t *lds) {
   using G = Geo<ID, SH>;
   using L = Layout<G>;
   const int lane = lane_id();
@@ -1019,19 +1021,41 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
           sbyte = rm_decode_pair<G::MULT>(blk);
         else
           sbyte = rm_decode_block<G::MULT>(blk);
-        if (fl < avail && lane < BPP) lds8[L::sym(g0 + q, b)] = (uint8_t)sbyte;
+        if (fl < avail && lane < BPP) lds8[L::sym(row0 + g0 + q, b)] = (uint8_t)sbyte;
         ++passes;
       }
       wave_sync();
     }
   }
-  // one Reed-Solomon word per lane, or per pair of lanes l, l + 32 when the
-  // tile has at most 32 items; lanes past the tile decode a copy of its first
-  // item and store nothing
+}
+
+// Symbol-table rows whose Reed-Solomon words are still to be decoded: rows
+// 0 .. fill - 1 of one segment, row r holding item row_item of lane r.
+// Consecutive tiles of a workgroup fill it, and it is decoded in one pass
+// (rs_flush) when the next tile would not fit in 32 rows, when the segment
+// changes and at the end, so that a workgroup with several small tiles pays
+// the Reed-Solomon stage's fixed cost per 32 words, not per tile.
+struct Pending {
+  int fill;
+  uint32_t row_item;
+};
+
+// S6-S10 of the pending rows: one Reed-Solomon word per lane pair l, l + 32
+// (at most 32 rows; always for the compact layout), or per lane (33 .. 64
+// rows); lanes past the rows decode a copy of row 0 and store nothing
+template <int ID, int OP, int SH>
+__device__ __forceinline__ void rs_flush(const SegDev &sg, Pending &pd, uint32_t *lds, GfTab exp4,
+                                         GfTab log4) {
+  using G = Geo<ID, SH>;
+  using L = Layout<G>;
+  const int lane = lane_id();
+  uint8_t *const lds8 = (uint8_t *)lds;
+  const int nt = pd.fill;
   const bool pair = G::COMPACT || nt <= 32;
   const int s = pair ? (lane & 31) : lane;
   const int slot = s < nt ? s : 0;
-  const uint32_t item = item0 + (uint32_t)slot;
+  const uint32_t mine = pair ? halves(pd.row_item).lo : pd.row_item;  // item of row s
+  const uint32_t item = s < nt ? mine : rdlane(pd.row_item, 0);
   bool active = s < nt;
   bool bad_key = false;
   if constexpr (OP == OP_KEYED) {
@@ -1052,20 +1076,27 @@ __device__ __forceinline__ void run_sub(const SegDev &sg, uint32_t item0, int nt
       atomicAdd(sg.ks_bad, 1ull);
     }
   }
-  wave_sync();
+  wave_sync();  // the rows are refilled after this
+  pd.fill = 0;
 }
 
-// a tile of nt <= 64 items; the compact layout takes it 32 items at a time
+// a tile of nt <= 64 items, in pieces of at most TROWS (32 for the compact
+// layout): each piece's symbols go after the pending rows, which are decoded
+// first when the piece would not fit in 32 rows; a piece of more than 32
+// items is decoded at once (one word per lane)
 template <int ID, int OP, int SH>
 __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int nt, uint32_t *lds,
-                                         GfTab exp4, GfTab log4) {
+                                         GfTab exp4, GfTab log4, Pending &pd) {
   using G = Geo<ID, SH>;
-  if constexpr (G::COMPACT) {
-    for (int s0 = 0; s0 < nt; s0 += G::TROWS)
-      run_sub<ID, OP, SH>(sg, item0 + (uint32_t)s0, nt - s0 < G::TROWS ? nt - s0 : G::TROWS, lds,
-                          exp4, log4);
-  } else {
-    run_sub<ID, OP, SH>(sg, item0, nt, lds, exp4, log4);
+  const int lane = lane_id();
+  for (int s0 = 0; s0 < nt; s0 += G::TROWS) {
+    const int sub = nt - s0 < G::TROWS ? nt - s0 : G::TROWS;
+    if (pd.fill > 0 && pd.fill + sub > 32) rs_flush<ID, OP, SH>(sg, pd, lds, exp4, log4);
+    const uint32_t first = item0 + (uint32_t)s0;
+    symbols<ID, OP, SH>(sg, first, sub, pd.fill, lds);
+    if (lane >= pd.fill && lane < pd.fill + sub) pd.row_item = first + (uint32_t)(lane - pd.fill);
+    pd.fill += sub;
+    if (pd.fill > 32) rs_flush<ID, OP, SH>(sg, pd, lds, exp4, log4);
   }
 }
 
@@ -1081,17 +1112,33 @@ hqc_kernel(KArgs a) {
   extern __shared__ uint32_t lds[];
   const GfTab exp4 = gf_exp_tab();
   const GfTab log4 = gf_log_tab();
+  constexpr int SH1 = MASK == 1u ? SH : 0, SH3 = MASK == 2u ? SH : 0;
+  Pending pd{0, 0u};
+  int cur = 0;  // segment of the pending rows
   for (uint32_t unit = blockIdx.x; unit < a.total; unit += gridDim.x) {
     int s = 0;
     if (a.nseg > 1 && unit >= a.seg[1].first) s = 1;
     if (a.nseg > 2 && unit >= a.seg[2].first) s = 2;
+    if (pd.fill > 0 && s != cur) {  // the segment changes: decode its rows first
+      const SegDev &ps = a.seg[cur];
+      if ((MASK & 1u) && ps.pid == 1) rs_flush<1, OP, SH1>(ps, pd, lds, exp4, log4);
+      if ((MASK & 2u) && ps.pid == 3) rs_flush<3, OP, SH3>(ps, pd, lds, exp4, log4);
+      if ((MASK & 4u) && ps.pid == 5) rs_flush<5, OP, 0>(ps, pd, lds, exp4, log4);
+    }
+    cur = s;
     const SegDev &sg = a.seg[s];
     const uint32_t item0 = (unit - sg.first) * a.tile;
     const uint32_t left = sg.count - item0;
     const int nt = (int)(left < a.tile ? left : a.tile);
-    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP, (MASK == 1u ? SH : 0)>(sg, item0, nt, lds, exp4, log4);
-    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP, (MASK == 2u ? SH : 0)>(sg, item0, nt, lds, exp4, log4);
-    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP, 0>(sg, item0, nt, lds, exp4, log4);
+    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP, SH1>(sg, item0, nt, lds, exp4, log4, pd);
+    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP, SH3>(sg, item0, nt, lds, exp4, log4, pd);
+    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP, 0>(sg, item0, nt, lds, exp4, log4, pd);
+  }
+  if (pd.fill > 0) {
+    const SegDev &ps = a.seg[cur];
+    if ((MASK & 1u) && ps.pid == 1) rs_flush<1, OP, SH1>(ps, pd, lds, exp4, log4);
+    if ((MASK & 2u) && ps.pid == 3) rs_flush<3, OP, SH3>(ps, pd, lds, exp4, log4);
+    if ((MASK & 4u) && ps.pid == 5) rs_flush<5, OP, 0>(ps, pd, lds, exp4, log4);
   }
 }
 

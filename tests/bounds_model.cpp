@@ -73,17 +73,26 @@ template <int ID, int SH> void check_decrypt(const char *name) {
           CHECK(name, blk >= L::rb(q) && blk + G::BLK - 1 < L::rb(q) + G::RB, "block inside its slot",
                 blk + G::BLK, L::rb(q) + G::RB);
           if (fl < avail && lane < L::BPP) {
-            const int so = L::sym(g0 + q, b);
             CHECK(name, g0 + q < nt && b < G::n1, "symbol of a tile row", g0 + q, nt);
-            CHECK(name, so >= G::A_BYTES && so < G::LDS_BYTES, "symbol store inside the table", so,
-                  G::LDS_BYTES);
+            // rows follow the pending rows of earlier tiles: a piece of at
+            // most 32 items starts at any row0 with row0 + nt <= 32, a larger
+            // one at row 0
+            const int row0_max = nt <= 32 ? 32 - nt : 0;
+            for (int row0 = 0; row0 <= row0_max; row0 += row0_max > 0 ? row0_max : 1) {
+              const int so = L::sym(row0 + g0 + q, b);
+              CHECK(name, row0 + g0 + q < G::TROWS, "symbol row inside the table", row0 + g0 + q,
+                    G::TROWS);
+              CHECK(name, so >= G::A_BYTES && so < G::LDS_BYTES, "symbol store inside the table",
+                    so, G::LDS_BYTES);
+            }
           }
         }
         ++passes;
       }
       if (last) CHECK(name, passes * L::BPP >= avail, "every block of the group decoded", passes, avail);
     }
-    // S6-S10: each lane (or lane pair) reads one tile row's symbols
+    // S6-S10: each lane (or lane pair) reads one pending row's symbols
+    // (nt rows pending; at most 32 for the pair form, up to TROWS otherwise)
     const bool pair = G::COMPACT || nt <= 32;
     for (int lane = 0; lane < 64; ++lane) {
       const int s = pair ? (lane & 31) : lane;

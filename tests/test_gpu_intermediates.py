@@ -18,13 +18,14 @@ pytestmark = pytest.mark.gpu
 
 
 
-@pytest.mark.parametrize("pid,tile", [(1, 32), (1, 64), (3, 32), (3, 64), (5, 32)])
-def test_intermediates_match_checker_components(pid, tile):
+@pytest.mark.parametrize("pid,tile,grid", [(1, 32, 0), (1, 64, 0), (3, 32, 0), (3, 64, 0), (5, 32, 0),
+                                           (1, 7, 2), (5, 5, 3)])
+def test_intermediates_match_checker_components(pid, tile, grid):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2512_12904_amd import hqc
-    print("case: intermediates pid=%d tile=%d" % (pid, tile), flush=True)
+    print("case: intermediates pid=%d tile=%d grid=%d" % (pid, tile, grid), flush=True)
     p = datasets.sizes(pid)
     par = oracle.param(pid)
     n, n1, n2, k = par["n"], par["n1"], par["n2"], par["k"]
@@ -39,7 +40,7 @@ def test_intermediates_match_checker_components(pid, tile):
     du = torch.from_numpy(u.view(np.int64)).cuda()
     dv = torch.from_numpy(v.view(np.int64)).cuda()
     dy = torch.from_numpy(y.view(np.int32)).cuda()
-    m, rec = hqc.decrypt_debug(pid, du, dv, dy, tile=tile)
+    m, rec = hqc.decrypt_debug(pid, du, dv, dy, tile=tile, grid=grid)
     m = m.cpu().numpy()
     # the debug kernel decrypts exactly like the plain one
     assert np.array_equal(m, hqc.decrypt_batch(pid, du, dv, dy, tile=tile).cpu().numpy())

@@ -110,11 +110,12 @@ def test_decode_random_words_match_oracle(hqc, pid):
 
 
 @pytest.mark.parametrize("pid", [1, 3, 5])
-@pytest.mark.parametrize("tile", [1, 31, 32, 33, 64])
+@pytest.mark.parametrize("tile", [1, 5, 16, 31, 32, 33, 64])
 def test_tile_sizes(hqc, pid, tile):
     # tiles of at most 32 items decode each Reed-Solomon word on a pair of
-    # lanes, larger ones on one lane; 200 = 6 * 33 + 2 also leaves a ragged
-    # last tile
+    # lanes (the words of consecutive small tiles of a workgroup together,
+    # up to 32), larger ones on one lane; 200 = 6 * 33 + 2 also leaves a
+    # ragged last tile
     say("case: pid=%d tile=%d grid=3" % (pid, tile))
     d = datasets.stress(pid, 200, 0x600 + tile)
     got = host(hqc.decode_batch(pid, dev(d["r"]), grid=3, tile=tile))
@@ -273,14 +274,16 @@ def test_structured_beyond_radius_matches_oracle(hqc, pid):
     assert (host(hqc.decrypt_batch(pid, dev(z), dev(r), dev(y))) == got).all()
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 1, 3, 20])
 def test_mixed_kernel_beyond_radius_matches_oracle(hqc, tile):
     """The three-set kernel (the instance the decoder-stress launch runs) on
     the inputs of the single-set beyond-radius tests: random ciphertexts with
     arbitrary keys, uniformly random received words and the structured edge
     words, all three sets in one launch each, every byte against the oracle.
     Tile 0 is the library's choice (lane pairs at these sizes), 64 the
-    one-lane Reed-Solomon form for HQC-1 and HQC-3."""
+    one-lane Reed-Solomon form for HQC-1 and HQC-3; small tiles on small
+    grids give each workgroup many tiles, whose words are decoded together
+    and whose run crosses from one parameter set to the next."""
     say("case: mixed kernel beyond radius tile=%d" % tile)
     sets = (1, 3, 5)
     rnd = {pid: _random_inputs(pid) for pid in sets}
@@ -311,7 +314,7 @@ def test_mixed_kernel_beyond_radius_matches_oracle(hqc, tile):
         assert (host(o) == host(o2)).all()
 
 
-@pytest.mark.parametrize("tile", [0, 64])
+@pytest.mark.parametrize("tile", [0, 64, 3])
 def test_keyed_kernels_beyond_radius_match_oracle(hqc, tile):
     """The keyed kernel (the instance the serving loop runs), per set and as
     one mixed launch, on random ciphertexts and on the structured edge words
