@@ -334,15 +334,12 @@ def committed_counters(name, launch=None):
     return e
 
 
-def timed_launch(pid, tuned):
-    """(shape, tile, grid) of the timed launches of a set, when known: the
-    autotuner's entry, or the configuration given on the command line."""
-    if pid in tuned:
-        t = tuned[pid]
-        return {"shape": t["shape"], "tile": t["tile"], "grid": t["grid"]}
-    if GRID and TILE and shape_for(pid):
-        return {"shape": shape_for(pid), "tile": TILE, "grid": GRID}
-    return None
+def timed_launch(hqc, pid, count):
+    """(shape, tile, grid) of the timed launches of a set: what the library
+    resolves for these knobs (the autotuner's table entry when the knobs are
+    left at 0, else the built-in choice)."""
+    sh, t, g = hqc.launch_config(pid, count, GRID, TILE, shape_for(pid))
+    return {"shape": sh, "tile": t, "grid": g}
 
 
 def copy_calibration(mib, device):
@@ -762,8 +759,9 @@ def main():
             u = v = y = m = out = None
             r.update(kem_bench(hqc, pid, args.count, 0xC0DE + pid, dev))
         r["hbm_GBps"] = hbm_bytes(pid) * args.count / (r["ms_mean"] / 1e3) / 1e9
-        tl = timed_launch(pid, tuned)
-        cc = committed_counters("HQC-%d" % pid, tl) if (args.count == 65536 and tl) else None
+        tl = timed_launch(hqc, pid, args.count)
+        r["launch"] = {"shape": "AB"[tl["shape"] - 1], "tile": tl["tile"], "grid": tl["grid"]}
+        cc = committed_counters("HQC-%d" % pid, tl) if args.count == 65536 else None
         if cc:
             # issue-slot fraction of the VALU from the committed counters of
             # this kernel source, beside the op-model fraction
@@ -805,11 +803,10 @@ def main():
         "config": {"workload": "HQC-%d PKE decrypt, batch %d in one persistent hipGraph launch"
                                % (pid0, args.count), "param_set": "HQC-%d" % pid0,
                    "batch": args.count,
-                   "launch": "hipGraph, persistent grid, %s" % (
-                       "shape %s, tile %d x grid %d from the autotuner" % (
-                           "AB"[tuned[pid0]["shape"] - 1], tuned[pid0]["tile"], tuned[pid0]["grid"])
-                       if pid0 in tuned else "shape %d / tile %d / grid %d (0 = library default)"
-                       % (shape_for(pid0), TILE, GRID))},
+                   "launch": "hipGraph, persistent grid, shape %s, tile %d x grid %d (%s)" % (
+                       main_r["launch"]["shape"], main_r["launch"]["tile"], main_r["launch"]["grid"],
+                       "autotuner" if pid0 in tuned else
+                       "command line" if (GRID or TILE or SHAPE) else "library default")},
         "gpu": gpu_info(dev),
         "p50_launch_ms": main_r["ms_p50"],
         "p99_launch_ms": main_r["ms_p99"],
@@ -817,9 +814,9 @@ def main():
                                    for kk, vv in r.items()} for k, r in results.items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "TOP/s (int32)", "frac": achieved / PEAK_INT_OPS,
-                     "traffic": ((committed_counters("HQC-%d" % pid0, timed_launch(pid0, tuned))
-                                  or {}).get("traffic_bytes")
-                                 if (args.count == 65536 and timed_launch(pid0, tuned)) else None),
+                     "traffic": ((committed_counters("HQC-%d" % pid0,
+                                                     timed_launch(hqc, pid0, args.count))
+                                  or {}).get("traffic_bytes") if args.count == 65536 else None),
                      "traffic_algorithmic": hbm_bytes(pid0) * args.count,
                      "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
                      "kernel_ms": main_r["ms_mean"]},

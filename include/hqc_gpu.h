@@ -325,17 +325,18 @@ void hqc_shutdown(void);
  * The decryption kernels take three launch parameters that never change the
  * results: the kernel shape (params->shape: RM blocks per lane or per lane
  * pair, LDS layout, wavefronts per SIMD), the persistent grid (workgroups)
- * and the tile (ciphertexts per workgroup tile, which also picks the
- * Reed-Solomon mapping: two lanes per word for tiles of at most 32, one
- * lane per word above).  The library keeps a table, per device, parameter
- * set and batch-size bucket (the power of two at or above count), of the
- * configuration to use when a single-set call leaves params->grid,
- * params->tile and params->shape at 0; without an entry it uses shape A
- * (shape B for HQC-1 once count fills B's occupancy grid with tiles of 32),
- * the occupancy grid and tile = ceil(count / grid), at most 64 (32 for HQC-1
- * decryption).  Because the
- * kernels' time does not depend on the data (constant time), configurations
- * can be timed on random inputs. */
+ * and the tile (ciphertexts per workgroup tile; a workgroup decodes the
+ * Reed-Solomon words of consecutive tiles together, two lanes per word in
+ * passes of up to 32 words, one lane per word in larger ones).  The library
+ * keeps a table, per device, parameter set and batch-size bucket (the power
+ * of two at or above count), of the configuration to use when a single-set
+ * call leaves params->grid, params->tile and params->shape at 0.  Without an
+ * entry, and for every mixed-set call, it chooses what the caller left open:
+ * shape B for single-set HQC-1 and HQC-3 once count gives B's occupancy
+ * grid 16 items per workgroup, else shape A; the occupancy grid of the shape;
+ * and the largest power-of-two tile (1 .. 64) not above count / grid.
+ * Because the kernels' time does not depend on the data (constant time),
+ * configurations can be timed on random inputs. */
 typedef struct hqc_tune_report {
   int32_t param_id;
   int32_t tile, grid;            /* chosen configuration (now in the table) */
@@ -372,6 +373,14 @@ int hqc_tune_set(int param_id, size_t count, int tile, int grid, int shape);
 int hqc_tune_get(int param_id, size_t count, int *tile, int *grid, int *shape);
 /* Empties the table (all devices). */
 void hqc_tune_clear(void);
+/* The launch that hqc_decrypt_batch(params, ..., count) makes on the current
+ * device: *shape (1 = A, 2 = B), *tile (items per tile) and *grid (persistent
+ * workgroups, at most the number of tiles) -- params' own values where set,
+ * else the table's entry, else the built-in choice.  Launches nothing.
+ * HQC_EINVAL: bad params or id, NULL pointers, count 0 or above
+ * HQC_MAX_COUNT, or shape B for a set without it; HQC_EHIP: no device. */
+int hqc_launch_config(const hqc_params_t *params, size_t count, int *shape, int *tile,
+                      int *grid);
 
 #ifdef __cplusplus
 }

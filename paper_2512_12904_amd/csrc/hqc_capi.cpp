@@ -193,18 +193,15 @@ uint32_t assign_tiles(hqc::KArgs &a, uint32_t tile) {
   return t;
 }
 
-int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
-  hipStream_t st = (hipStream_t)p->stream;
-  uint64_t items = 0;
-  for (uint32_t s = 0; s < a.nseg; ++s) items += a.seg[s].count;
-  if (items == 0) return HQC_OK;
+// The launch of `items` items: the caller's shape, tile and grid where set,
+// else the tuned table's entry (single-set calls that leave all three open),
+// else the built-in choice.  shape out: 0 (A) or 1 (B).
+int resolve_launch(int op, const hqc_params_t *p, unsigned mask, uint64_t items, int *shape_out,
+                   uint32_t *tile_out, int *grid_out) {
   int grid = p->grid;
   uint32_t tile = (uint32_t)p->tile;
-  // kernel shape: the caller's (1 = shape 0, 2 = shape 1), else the tuned
-  // table's, else the built-in choice
   int shape = p->shape - 1;
   if (shape == 1 && !hqc::shape_exists(op, mask, 1)) return HQC_EINVAL;
-  bool tuned = false;
   if (grid <= 0 && tile == 0 && p->shape == 0 && (mask == 1u || mask == 2u || mask == 4u)) {
     int tt = 0, tg = 0, ts = 0;
     if (tuned_lookup(mask == 1u ? 1 : mask == 2u ? 3 : 5, items, &tt, &tg, &ts) &&
@@ -212,35 +209,26 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
       tile = (uint32_t)tt;
       grid = tg;
       shape = ts;
-      tuned = true;
     }
   }
-  if (shape < 0) {
-    // built-in: HQC-1's shape 1 once the batch fills its larger occupancy
-    // grid with tiles of 32 items (measured faster there, slower below)
-    shape = 0;
-    if (mask == 1u && hqc::shape_exists(op, mask, 1)) {
-      int g1 = 0;
-      int rc = default_grid(op, mask, &g1, 1);
-      if (rc) return rc;
-      if (items >= 32ull * (uint64_t)g1) shape = 1;
-    }
-  }
-  (void)tuned;
-  int full = 0;
+  const int rc = hqc::builtin_launch(op, mask, items, &shape, &tile, &grid);
+  if (rc) return rc;
+  *shape_out = shape;
+  *tile_out = tile;
+  *grid_out = grid;
+  return HQC_OK;
+}
+
+int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
+  hipStream_t st = (hipStream_t)p->stream;
+  uint64_t items = 0;
+  for (uint32_t s = 0; s < a.nseg; ++s) items += a.seg[s].count;
+  if (items == 0) return HQC_OK;
+  int grid = 0, shape = 0;
+  uint32_t tile = 0;
   {
-    int rc = default_grid(op, mask, &full, shape);
+    const int rc = resolve_launch(op, p, mask, items, &shape, &tile, &grid);
     if (rc) return rc;
-  }
-  if (grid <= 0) grid = full;
-  if (tile == 0) {
-    // enough tiles to give every resident workgroup one, at most 64 items
-    // each -- at most 32 for HQC-1 decryption, whose lane-pair Reed-Solomon
-    // form (tiles of up to 32) measured faster than the one-lane form there
-    // (131,072 items: 0.65 vs 0.73 ms); decoding keeps the larger tiles
-    const uint64_t cap = (mask == 1u && op != hqc::OP_DECODE) ? 32 : 64;
-    uint64_t per = (items + (uint64_t)grid - 1) / (uint64_t)grid;
-    tile = (uint32_t)(per < 1 ? 1 : per > cap ? cap : per);
   }
   assign_tiles(a, tile);
   if ((uint32_t)grid > a.total) grid = (int)a.total;
@@ -331,6 +319,41 @@ int run_segments(int op, const hqc_params_t *p, const hqc_segment_t *segs, int n
 namespace hqc {
 int occupancy_grid(int op, unsigned mask, int shape, int *out) {
   return default_grid(op, mask, out, shape);
+}
+
+// The built-in launch, from autotuner sweeps over 256 .. 262,144 items per
+// set (lane-pair Reed-Solomon words of consecutive tiles decoded together):
+//  * shape 1 (three waves per SIMD) for the single-set HQC-1 and HQC-3
+//    kernels once the batch gives its occupancy grid tiles of 16 items;
+//    below that, shape 0;
+//  * the occupancy grid;
+//  * tiles of the largest power of two not above items / grid (1 .. 64):
+//    enough tiles for every resident workgroup, and tiles as large as that
+//    allows, since a 64-word Reed-Solomon pass costs fewer instructions per
+//    word than two 32-word ones.
+// Only what the caller left open is chosen: shape < 0, grid <= 0, tile 0.
+int builtin_launch(int op, unsigned mask, uint64_t items, int *shape, uint32_t *tile,
+                   int *grid) {
+  if (*shape < 0) {
+    *shape = 0;
+    if (shape_exists(op, mask, 1)) {
+      int g1 = 0;
+      const int rc = default_grid(op, mask, &g1, 1);
+      if (rc) return rc;
+      if (items >= 16ull * (uint64_t)g1) *shape = 1;
+    }
+  }
+  if (*grid <= 0) {
+    const int rc = default_grid(op, mask, grid, *shape);
+    if (rc) return rc;
+  }
+  if (*tile == 0) {
+    const uint64_t per = items / (uint64_t)*grid;
+    uint32_t t = 1;
+    while (t < 64 && 2ull * t <= per) t *= 2;
+    *tile = t;
+  }
+  return HQC_OK;
 }
 }  // namespace hqc
 
@@ -953,6 +976,24 @@ int hqc_tune_get(int param_id, size_t count, int *tile, int *grid, int *shape) {
     *shape += 1;
   else
     *tile = *grid = *shape = 0;
+  return HQC_OK;
+}
+
+int hqc_launch_config(const hqc_params_t *params, size_t count, int *shape, int *tile,
+                      int *grid) {
+  if (!params || !shape || !tile || !grid || count == 0 || count > HQC_MAX_COUNT) return HQC_EINVAL;
+  const int rc = check_params(params);
+  if (rc) return rc;
+  const unsigned mask = (unsigned)pid_bit(params->param_id);
+  if (!mask) return HQC_EINVAL;
+  int sh = 0, g = 0;
+  uint32_t t = 0;
+  const int r2 = resolve_launch(hqc::OP_DECRYPT, params, mask, count, &sh, &t, &g);
+  if (r2) return r2;
+  const uint64_t tiles = (count + t - 1) / t;
+  *shape = sh + 1;
+  *tile = (int)t;
+  *grid = (uint64_t)g > tiles ? (int)tiles : g;
   return HQC_OK;
 }
 

@@ -63,5 +63,9 @@ hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t s
 // the occupancy grid (CUs x resident workgroups) of a kernel on the current
 // device, cached (hqc_capi.cpp)
 int occupancy_grid(int op, unsigned mask, int shape, int *out);
+// the library's built-in launch of `items` items when the caller and the
+// tuned table leave it open: shape (-1 = choose), tile and grid (hqc_capi.cpp)
+int builtin_launch(int op, unsigned mask, uint64_t items, int *shape, uint32_t *tile,
+                   int *grid);
 
 }  // namespace hqc

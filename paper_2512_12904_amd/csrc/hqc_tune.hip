@@ -92,21 +92,20 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
                      0x7E59ull + param_id);
   if (hipGetLastError() != hipSuccess) return HQC_EHIP;
 
-  // the built-in default first (the library's choice for this count: shape
-  // B for HQC-1 once the batch fills B's grid with tiles of 32, else A; the
-  // occupancy grid and enough tiles for it)
-  const int h_shape = (mask == 1u && nshape == 2 && count >= 32 * (size_t)full[1]) ? 1 : 0;
-  const int h_full = full[h_shape];
-  const size_t h_cap = mask == 1u ? 32 : 64;  // as the library's built-in choice
-  const int h_tile =
-      (int)std::min<size_t>(h_cap, std::max<size_t>(1, (count + h_full - 1) / h_full));
+  // the library's built-in choice first
+  int h_shape = -1, h_full = 0;  // built-in shape and its occupancy grid
+  uint32_t h_tile = 0;
+  {
+    const int rc = hqc::builtin_launch(hqc::OP_DECRYPT, mask, count, &h_shape, &h_tile, &h_full);
+    if (rc != HQC_OK) return rc;
+  }
   struct Cand {
     int shape, tile, grid;
     bool operator==(const Cand &o) const {
       return shape == o.shape && tile == o.tile && grid == o.grid;
     }
   };
-  std::vector<Cand> cand{{h_shape, h_tile, h_full}};
+  std::vector<Cand> cand{{h_shape, (int)h_tile, h_full}};
   const int tiles[] = {1, 2, 4, 8, 16, 24, 32, 40, 48, 64};
   const int gnum[] = {2, 3, 4, 5, 6};  // grid = full * gnum / 4
   auto add = [&](int sh, int t, int grid) {

@@ -34,7 +34,7 @@ EXPORTS = (
     "hqc_encrypt_batch", "hqc_code_encode_batch", "hqc_kem_workspace_bytes", "hqc_kem_encaps_batch",
     "hqc_kem_decaps_batch", "hqc_kem_decaps_batch_noalloc", "hqc_fixed_weight_batch", "hqc_ring_workspace_bytes", "hqc_ring_default_threshold",
     "hqc_ring_mul_batch", "hqc_autotune_decrypt", "hqc_tune_set", "hqc_tune_get",
-    "hqc_tune_clear", "hqc_debug_bytes", "hqc_decrypt_debug",
+    "hqc_tune_clear", "hqc_launch_config", "hqc_debug_bytes", "hqc_decrypt_debug",
 )
 
 
@@ -128,6 +128,8 @@ def lib():
         L.hqc_tune_get.argtypes = [ctypes.c_int, sz, ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.hqc_tune_clear.restype = None
+        L.hqc_launch_config.argtypes = [ctypes.POINTER(Params), sz, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.hqc_tune_clear.argtypes = []
         L.hqc_debug_bytes.restype = ctypes.c_size_t
         L.hqc_debug_bytes.argtypes = [ctypes.c_int]
@@ -547,6 +549,16 @@ def tune_get(pid, count):
 
 def tune_clear():
     lib().hqc_tune_clear()
+
+
+def launch_config(pid, count, grid=0, tile=0, shape=0):
+    """(shape, tile, grid) of the launch decrypt_batch makes for count items
+    with these knobs (1 = shape A, 2 = shape B), on the current device."""
+    p = _params(pid, 0, grid, None, tile, shape)
+    sh, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().hqc_launch_config(ctypes.byref(p), count, ctypes.byref(sh), ctypes.byref(t),
+                                   ctypes.byref(g)), "hqc_launch_config")
+    return sh.value, t.value, g.value
 
 
 def decrypt_debug(pid, u, v, y, flags=0, grid=0, stream=None, tile=0):

@@ -91,6 +91,14 @@ def test_invalid_arguments_rejected_before_launch(gpu_lib):
     one = (gpu_lib.Segment * 1)()
     one[0].param_id = 1
     assert L.hqc_decrypt_mixed_keyed(ctypes.byref(p), None, one, 1) == gpu_lib.HQC_EINVAL
+    # launch-configuration query: NULL outputs, count 0, bad id or shape
+    i = ctypes.c_int()
+    r = ctypes.byref(i)
+    assert L.hqc_launch_config(ctypes.byref(p), 10, None, r, r) == gpu_lib.HQC_EINVAL
+    assert L.hqc_launch_config(ctypes.byref(p), 0, r, r, r) == gpu_lib.HQC_EINVAL
+    assert L.hqc_launch_config(None, 10, r, r, r) == gpu_lib.HQC_EINVAL
+    assert L.hqc_launch_config(ctypes.byref(P(4, 0, None, 0, 0)), 10, r, r, r) == gpu_lib.HQC_EINVAL
+    assert L.hqc_launch_config(ctypes.byref(P(5, 0, None, 0, 0, 2)), 10, r, r, r) == gpu_lib.HQC_EINVAL
 
 
 def test_host_pointer_rejected_without_gpu(gpu_lib):

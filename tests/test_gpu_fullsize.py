@@ -41,11 +41,13 @@ def dev(a):
     return torch.from_numpy(a).cuda()
 
 
-# launch configurations: the library's default, and the one the autotuner
-# picks for HQC-1 at this size on MI355X (shape B, tiles of 16, 3,072
-# workgroups), which bench.py times
-@pytest.mark.parametrize("pid,master,launch", [(1, 0x2, None), (1, 0x2, (2, 16, 3072)),
-                                               (3, 0x3, None), (5, 0x5, None)])
+# launch configurations: the library's default (at this size shape B, tiles
+# of 16, 3,072 workgroups for HQC-1 and HQC-3; shape A, tiles of 32, 2,048
+# workgroups for HQC-5 -- also the autotuner's choices on MI355X, which
+# bench.py times) and shape A for HQC-1 and HQC-3
+@pytest.mark.parametrize("pid,master,launch", [(1, 0x2, None), (1, 0x2, (1, 32, 2048)),
+                                               (3, 0x3, None), (3, 0x3, (1, 32, 2048)),
+                                               (5, 0x5, None)])
 def test_decrypt_65536_one_launch(hqc, pid, master, launch):
     import torch
     count = 65536

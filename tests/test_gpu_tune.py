@@ -24,6 +24,10 @@ def test_autotune_then_default_launch_matches_checker(pid):
     assert r["shape"] in ((1, 2) if pid != 5 else (1,)) and r["heuristic_shape"] in (1, 2)
     assert r["ms"] <= r["heuristic_ms"] + 1e-6
     assert hqc.tune_get(pid, count) == (r["tile"], r["grid"], r["shape"])
+    # the launch a default call makes is the tuned entry's; explicit knobs win
+    assert hqc.launch_config(pid, count) == (r["shape"], r["tile"], min(r["grid"],
+                                                                        -(-count // r["tile"])))
+    assert hqc.launch_config(pid, count, grid=64, tile=8, shape=1) == (1, 8, 64)
     d = datasets.pke(pid, count, 0x7A0 + pid)
     dev = "cuda"
     u = torch.from_numpy(d["u"].view(np.int64)).to(dev)
@@ -45,3 +49,29 @@ def test_autotune_rejects_bad_arguments():
             hqc.autotune_decrypt(*args)
     with pytest.raises(hqc.HqcError):
         hqc.autotune_decrypt(1, (1 << 20) + 1, 1)
+
+
+def test_builtin_launch_config():
+    """Without a table entry: shape B for HQC-1 and HQC-3 once the batch gives
+    B's occupancy grid 16 items per workgroup, the occupancy grid, and the
+    largest power-of-two tile not above count / grid (at most 64)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12904_amd import hqc
+    hqc.tune_clear()
+    for pid in (1, 3, 5):
+        full_a = hqc.launch_config(pid, 1 << 20, shape=1)[2]
+        full_b = hqc.launch_config(pid, 1 << 20, shape=2)[2] if pid != 5 else None
+        for count in (1, 100, 4096, 16384, 65536, 262144):
+            sh, t, g = hqc.launch_config(pid, count)
+            want_sh = 2 if (full_b and count >= 16 * full_b) else 1
+            full = full_b if want_sh == 2 else full_a
+            want_t = 1
+            while want_t < 64 and 2 * want_t <= count // full:
+                want_t *= 2
+            assert (sh, t, g) == (want_sh, want_t, min(full, -(-count // want_t))), (pid, count)
+    with pytest.raises(hqc.HqcError):
+        hqc.launch_config(5, 100, shape=2)
+    with pytest.raises(hqc.HqcError):
+        hqc.launch_config(1, 0)
