@@ -91,7 +91,12 @@ typedef struct hqc_params {
   void *stream;     /* hipStream_t, or NULL for the null stream */
   int32_t grid;     /* persistent workgroups; 0 = chosen by the library */
   int32_t tile;     /* items per workgroup tile, 1..64; 0 = chosen by the library.
-                       Results never depend on grid or tile. */
+                       In a launch over several sets this is the HQC-1
+                       tile, and the other sets' tiles are that divided by
+                       their relative time per item (HQC-3 about 1.5-2x,
+                       HQC-5 3-4x) and rounded to a power of two, but not
+                       below min(tile, 4), so that the tiles take about as
+                       long.  Results never depend on grid or tile. */
   int32_t shape;    /* kernel shape: 0 = chosen by the library, 1 = shape A, 2 =
                        shape B (single-set HQC-1 or HQC-3 decryption, decoding
                        and keyed decryption only; HQC_EINVAL elsewhere).

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -181,14 +182,60 @@ bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid, int *shape) {
   return true;
 }
 
-// Splits the segments into tiles of `tile` items; returns the tile count.
-uint32_t assign_tiles(hqc::KArgs &a, uint32_t tile) {
+// Relative time per item of the sets in the shape-A kernels (HQC-1 = 64),
+// from single-set launches on MI355X: decryption (and keyed decryption) of
+// 65,536 items (0.382 / 0.821 / 1.524 ms), decoding of 262,144 words
+// (0.587 / 0.897 / 1.718 ms).
+uint32_t set_cost(int op, int pid) {
+  const bool dec = op == hqc::OP_DECODE;
+  switch (pid) {
+    case 1: return 64;
+    case 3: return dec ? 98 : 137;
+    case 5: return dec ? 187 : 255;
+    default: return 64;
+  }
+}
+
+// Items of a launch in HQC-1 units of work (the cost-weighted count when
+// several sets are present).
+uint64_t weighted_items(int op, const hqc::KArgs &a) {
+  uint64_t w = 0, nonempty = 0, plain = 0;
+  for (uint32_t s = 0; s < a.nseg; ++s) {
+    plain += a.seg[s].count;
+    w += (uint64_t)a.seg[s].count * set_cost(op, a.seg[s].pid) / 64;
+    nonempty += a.seg[s].count > 0;
+  }
+  return nonempty > 1 ? w : plain;
+}
+
+// Splits the segments into tiles; returns the tile count.  With one set,
+// tiles of `tile` items.  With several, `tile` is the HQC-1 tile and the
+// other sets' tiles are scaled down by their cost per item, to the nearest
+// power of two (whole Reed-Solomon passes of 16 or 32 words), so that the
+// tiles of the launch take about the same time and the workgroups, which
+// take tiles round-robin, finish together -- but not below 4 items (or
+// `tile`, if smaller): a tile's fixed cost (loads before the pipeline
+// fills, a Reed-Solomon pass) outweighs the balance below that.  Measured
+// against unscaled tiles: 65,536 ciphertexts 50/30/20 % HQC-1/3/5 0.90 vs
+// 1.28 ms, 1,048,576 decoder words 3.94 vs 4.07 ms.
+uint32_t assign_tiles(int op, hqc::KArgs &a, uint32_t tile) {
+  uint32_t nonempty = 0;
+  for (uint32_t s = 0; s < a.nseg; ++s) nonempty += a.seg[s].count > 0;
+  const uint32_t floor_tile = tile < 4 ? tile : 4;
   uint32_t t = 0;
   for (uint32_t s = 0; s < a.nseg; ++s) {
-    a.seg[s].first = t;
-    t += (a.seg[s].count + tile - 1) / tile;
+    hqc::SegDev &sg = a.seg[s];
+    uint32_t ts = tile;
+    if (nonempty > 1) {
+      const uint32_t c = set_cost(op, sg.pid);
+      const long e = std::lround(std::log2((double)tile * 64.0 / (double)c));
+      ts = e <= 0 ? 1u : e >= 6 ? 64u : (1u << e);
+      ts = ts < floor_tile ? floor_tile : ts;
+    }
+    sg.tile = ts;
+    sg.first = t;
+    t += (sg.count + ts - 1) / ts;
   }
-  a.tile = tile;
   a.total = t;
   return t;
 }
@@ -227,10 +274,10 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
   int grid = 0, shape = 0;
   uint32_t tile = 0;
   {
-    const int rc = resolve_launch(op, p, mask, items, &shape, &tile, &grid);
+    const int rc = resolve_launch(op, p, mask, weighted_items(op, a), &shape, &tile, &grid);
     if (rc) return rc;
   }
-  assign_tiles(a, tile);
+  assign_tiles(op, a, tile);
   if ((uint32_t)grid > a.total) grid = (int)a.total;
   if (p->flags & HQC_F_PER_ITEM_LAUNCH) {
     // Baseline mode: the same kernel, one launch per item (count = 1).
@@ -243,10 +290,10 @@ int run(int op, const hqc_params_t *p, hqc::KArgs &a, unsigned mask) {
         std::memset(&one, 0, sizeof one);
         one.nseg = 1;
         one.total = 1;
-        one.tile = 1;
         hqc::SegDev &o = one.seg[0];
         o = sg;
         o.first = 0;
+        o.tile = 1;
         o.count = 1;
         const size_t in_words = op == hqc::OP_DECODE ? (size_t)si.v_words : (size_t)si.u_words;
         o.u = sg.u + (size_t)i * in_words;

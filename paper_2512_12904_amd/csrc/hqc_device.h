@@ -83,6 +83,13 @@ template <int ID, int SH = 0> struct Geo {
 // check (tests) evaluates the same functions over every lane, shift, tile
 // row and pass against the LDS and buffer sizes.  Offsets are in dwords
 // from the start of the dynamic LDS, except the symbol tables (bytes).
+// The persistent grid's tile schedule: workgroup `block` of `grid` takes
+// tiles block, block + grid, block + 2 grid, ...; its first tile at or after
+// a segment's first tile `first`.
+__host__ __device__ constexpr uint32_t first_unit(uint32_t block, uint32_t grid, uint32_t first) {
+  return block >= first ? block : block + (first - block + grid - 1) / grid * grid;
+}
+
 template <class G> struct Layout {
   static constexpr int BPP = G::PAIR_RM ? 32 : 64;  // RM blocks per pass
   // decryption: received-word slot q starts at rb(q); dword d of a word sits

@@ -25,16 +25,17 @@ struct SegDev {
   uint32_t ks_cap;          // keyed only: slots in ks_y
   uint32_t count;
   uint32_t first;           // index of the segment's first tile in the launch
+  uint32_t tile;            // items per tile of this segment, 1 .. 64
   int32_t pid;              // 1, 3 or 5
 };
 
 // A launch is a list of tiles: up to `tile` consecutive items of one
-// segment, decoded by one wavefront.
+// segment, decoded by one wavefront.  Segments are stored in tile order
+// (seg[s + 1].first follows seg[s]'s last tile) and hold distinct sets.
 struct KArgs {
   SegDev seg[3];
   uint32_t nseg;
   uint32_t total;  // tiles
-  uint32_t tile;   // items per tile, 1 .. 64
 };
 
 // Per-parameter sizes as the kernels see them.

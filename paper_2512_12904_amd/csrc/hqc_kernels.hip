@@ -1105,6 +1105,25 @@ constexpr int kernel_waves(unsigned mask, int sh) {
   return sh == 1 ? (mask == 1u ? Geo<1, 1>::WAVES : Geo<3, 1>::WAVES) : 2;
 }
 
+// The tiles of segment s that this workgroup takes (units blockIdx.x,
+// blockIdx.x + gridDim.x, ... that fall in the segment), Reed-Solomon rows
+// pending across them and decoded at the end.
+template <int ID, int OP, int SH>
+__device__ __forceinline__ void run_segment(const KArgs &a, int s, uint32_t *lds, GfTab exp4,
+                                            GfTab log4) {
+  const SegDev &sg = a.seg[s];
+  const uint32_t end = s + 1 < (int)a.nseg ? a.seg[s + 1].first : a.total;
+  Pending pd{0, 0u};
+  for (uint32_t unit = first_unit(blockIdx.x, gridDim.x, sg.first); unit < end;
+       unit += gridDim.x) {
+    const uint32_t item0 = (unit - sg.first) * sg.tile;
+    const uint32_t left = sg.count - item0;
+    const int nt = (int)(left < sg.tile ? left : sg.tile);
+    run_tile<ID, OP, SH>(sg, item0, nt, lds, exp4, log4, pd);
+  }
+  if (pd.fill > 0) rs_flush<ID, OP, SH>(sg, pd, lds, exp4, log4);
+}
+
 template <int OP, unsigned MASK, int SH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kernel_waves(MASK, SH)))) void
 hqc_kernel(KArgs a) {
@@ -1113,33 +1132,19 @@ hqc_kernel(KArgs a) {
   const GfTab exp4 = gf_exp_tab();
   const GfTab log4 = gf_log_tab();
   constexpr int SH1 = MASK == 1u ? SH : 0, SH3 = MASK == 2u ? SH : 0;
-  Pending pd{0, 0u};
-  int cur = 0;  // segment of the pending rows
-  for (uint32_t unit = blockIdx.x; unit < a.total; unit += gridDim.x) {
-    int s = 0;
-    if (a.nseg > 1 && unit >= a.seg[1].first) s = 1;
-    if (a.nseg > 2 && unit >= a.seg[2].first) s = 2;
-    if (pd.fill > 0 && s != cur) {  // the segment changes: decode its rows first
-      const SegDev &ps = a.seg[cur];
-      if ((MASK & 1u) && ps.pid == 1) rs_flush<1, OP, SH1>(ps, pd, lds, exp4, log4);
-      if ((MASK & 2u) && ps.pid == 3) rs_flush<3, OP, SH3>(ps, pd, lds, exp4, log4);
-      if ((MASK & 4u) && ps.pid == 5) rs_flush<5, OP, 0>(ps, pd, lds, exp4, log4);
-    }
-    cur = s;
-    const SegDev &sg = a.seg[s];
-    const uint32_t item0 = (unit - sg.first) * a.tile;
-    const uint32_t left = sg.count - item0;
-    const int nt = (int)(left < a.tile ? left : a.tile);
-    if ((MASK & 1u) && sg.pid == 1) run_tile<1, OP, SH1>(sg, item0, nt, lds, exp4, log4, pd);
-    if ((MASK & 2u) && sg.pid == 3) run_tile<3, OP, SH3>(sg, item0, nt, lds, exp4, log4, pd);
-    if ((MASK & 4u) && sg.pid == 5) run_tile<5, OP, 0>(sg, item0, nt, lds, exp4, log4, pd);
+  // the segment of each parameter set (each set appears at most once); the
+  // sets run one after the other in straight-line code, so that no set's
+  // loop-invariant registers stay live through another set's loop
+  int s1 = -1, s3 = -1, s5 = -1;
+  for (int s = 0; s < (int)a.nseg; ++s) {
+    const int pid = a.seg[s].pid;
+    s1 = pid == 1 ? s : s1;
+    s3 = pid == 3 ? s : s3;
+    s5 = pid == 5 ? s : s5;
   }
-  if (pd.fill > 0) {
-    const SegDev &ps = a.seg[cur];
-    if ((MASK & 1u) && ps.pid == 1) rs_flush<1, OP, SH1>(ps, pd, lds, exp4, log4);
-    if ((MASK & 2u) && ps.pid == 3) rs_flush<3, OP, SH3>(ps, pd, lds, exp4, log4);
-    if ((MASK & 4u) && ps.pid == 5) rs_flush<5, OP, 0>(ps, pd, lds, exp4, log4);
-  }
+  if ((MASK & 1u) && s1 >= 0) run_segment<1, OP, SH1>(a, s1, lds, exp4, log4);
+  if ((MASK & 2u) && s3 >= 0) run_segment<3, OP, SH3>(a, s3, lds, exp4, log4);
+  if ((MASK & 4u) && s5 >= 0) run_segment<5, OP, 0>(a, s5, lds, exp4, log4);
 }
 
 template <int OP>

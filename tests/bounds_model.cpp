@@ -134,7 +134,46 @@ template <int ID> void check_encrypt(const char *name) {
 
 }  // namespace
 
+// The tile schedule of a launch over several segments: every tile is taken
+// by exactly one workgroup, inside its own segment, and its items lie inside
+// the segment.
+void check_schedule() {
+  const char *name = "tile schedule";
+  const uint32_t counts[][3] = {{1, 0, 0}, {64, 65, 1}, {0, 100, 7}, {1000, 999, 998},
+                                {32768, 19661, 13107}, {5, 0, 130}};
+  const uint32_t tiles[][3] = {{1, 1, 1}, {64, 30, 16}, {7, 3, 2}, {32, 15, 8}};
+  const uint32_t grids[] = {1, 3, 64, 2048, 3072};
+  for (const auto &c : counts)
+    for (const auto &t : tiles)
+      for (uint32_t grid : grids) {
+        uint32_t first[4], total = 0;
+        for (int s = 0; s < 3; ++s) {
+          first[s] = total;
+          total += (c[s] + t[s] - 1) / t[s];
+        }
+        first[3] = total;
+        if (grid > total && total > 0) grid = total;
+        if (total == 0) continue;
+        static unsigned char seen[1 << 20];
+        for (uint32_t u = 0; u < total; ++u) seen[u] = 0;
+        for (uint32_t b = 0; b < grid; ++b)
+          for (int s = 0; s < 3; ++s)
+            for (uint32_t u = hqc::first_unit(b, grid, first[s]); u < first[s + 1]; u += grid) {
+              CHECK(name, u % grid == b, "tile of another workgroup", u, b);
+              CHECK(name, u >= first[s], "tile before its segment", u, first[s]);
+              ++seen[u];
+              const uint32_t item0 = (u - first[s]) * t[s];
+              const uint32_t nt = c[s] - item0 < t[s] ? c[s] - item0 : t[s];
+              CHECK(name, item0 < c[s] && nt >= 1 && item0 + nt <= c[s], "items inside the segment",
+                    item0 + nt, c[s]);
+            }
+        for (uint32_t u = 0; u < total; ++u) CHECK(name, seen[u] == 1, "tile taken once", u, seen[u]);
+      }
+}
+
 int main() {
+  check_schedule();
+  std::printf("tile schedule ok\n");
   check_decrypt<1, 0>("decrypt HQC-1 shape A");
   std::printf("decrypt HQC-1 shape A ok\n");
   check_decrypt<1, 1>("decrypt HQC-1 shape B");

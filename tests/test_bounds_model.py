@@ -2,7 +2,8 @@
 functions the kernels call (Layout<G> in csrc/hqc_device.h) are evaluated by
 tests/bounds_model.cpp, built host-only with hipcc, for every instantiated
 geometry over every lane, product shift, tile size and RM pass, against the
-LDS layout and the device row sizes."""
+LDS layout and the device row sizes; and the persistent grid's tile
+schedule over segments of several sets with their own tile sizes."""
 import os
 import shutil
 import subprocess
@@ -24,4 +25,4 @@ def test_kernel_index_bounds(tmp_path):
                           stderr=subprocess.DEVNULL)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count(" ok") == 6, r.stdout
+    assert r.stdout.count(" ok") == 7, r.stdout
