@@ -39,6 +39,8 @@
 namespace hqc {
 namespace {
 
+constexpr bool kMfmaRm = true;
+
 // ---- S3-S5: one duplicated RM(1,7) block -> symbol byte ---------------------
 template <int MULT>
 __device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
@@ -244,6 +246,118 @@ __device__ __forceinline__ uint32_t rm_decode_pair(const uint32_t *blk) {
   const u16x2 drop = upper ? u16x2{64, 64} : u16x2{0, 0};
   kmax = kmax - drop;
   const uint32_t mine = kmax.x > kmax.y ? kmax.x : kmax.y;
+  const Halves both = halves(mine);
+  const uint32_t best = both.lo > both.hi ? both.lo : both.hi;
+  return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
+}
+
+// ---- S3-S5: one duplicated RM(1,7) block per lane pair, on the matrix cores ---
+// The correlations of the received block with the 256 codewords of RM(1,7)
+// are +-(128 MULT [u == 0] - 2 H(u)), where H = W F is the Walsh-Hadamard
+// transform of the copy counts F (W[u][k] = (-1)^popcount(u & k)): a dense
+// 128 x 128 by 128 x 32 integer product for the 32 blocks of a pass, run as
+// int8 MFMAs (v_mfma_i32_32x32x32_i8: 32 rows u of W times 32 positions k,
+// times the counts of 32 blocks, one block per column).  Lanes l and l + 32
+// hold block l mod 32.
+//
+// Positions are split over the four K steps t and the two half-waves h as
+// k = 32 t + 16 h + c: byte c (0 .. 15) of lane (j, h)'s B operand in step t
+// is F(32 t + 16 h + c) of block j -- the 16 bits 16h .. 16h + 15 of dword t
+// of the bit-sliced counts, spread to bytes.  The A operand of lane (i, h) in
+// M tile mt (rows u = 32 mt + i) and step t is then
+// W[32 mt + i][32 t + 16 h + c] = (-1)^(popcount(i & (16 h + c)) + popcount(mt & t)):
+// one per-lane tile A0 and its negation, chosen per (mt, t) at compile time.
+// The result of M tile mt in lane (j, h), register 4 rb + ri, is H(u) of
+// block j for u = 32 mt + 8 rb + 4 h + ri; the peak search is that of
+// rm_decode_pair on 16-bit pairs of these.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+template <int MULT>
+__device__ __forceinline__ uint32_t rm_decode_mfma(const uint32_t *blk) {
+  // an opaque copy of the lane number: A0 and the lane's shifts are rebuilt
+  // here (a dozen instructions) rather than hoisted and kept live
+  int lane = lane_id();
+  asm volatile("" : "+v"(lane));
+  const uint32_t h = (uint32_t)lane >> 5, i = (uint32_t)lane & 31u;
+  // bit-sliced counts of the four dwords (positions 32t .. 32t + 31); the
+  // lane keeps its 16 bits, moved down to bits 0 .. 15
+  uint32_t p0[4], p1[4], p2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint32_t x = blk[t], y = blk[4 + t], z = blk[8 + t];
+    const uint32_t sm = xor3(x, y, z), cy = maj3(x, y, z);
+    if constexpr (MULT == 3) {
+      p0[t] = sm;
+      p1[t] = cy;
+      p2[t] = 0;
+    } else {
+      const uint32_t d = blk[12 + t], f = blk[16 + t];
+      const uint32_t sm2 = xor3(sm, d, f), cy2 = maj3(sm, d, f);
+      p0[t] = sm2;
+      p1[t] = cy ^ cy2;
+      p2[t] = cy & cy2;
+    }
+    p0[t] >>= 16 * h;
+    p1[t] >>= 16 * h;
+    p2[t] >>= 16 * h;
+  }
+  // B operands: byte c of step t = F(32 t + 16 h + c); a nibble of a plane
+  // spreads to the low bit of 4 bytes by one multiply
+  i32x4 B[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      uint32_t v = (__builtin_amdgcn_ubfe(p0[t], 4 * d, 4) * 0x204081u) & 0x01010101u;
+      v += ((__builtin_amdgcn_ubfe(p1[t], 4 * d, 4) * 0x204081u) & 0x01010101u) << 1;
+      if constexpr (MULT == 5)
+        v += ((__builtin_amdgcn_ubfe(p2[t], 4 * d, 4) * 0x204081u) & 0x01010101u) << 2;
+      B[t][d] = (int)v;
+    }
+  // A0: byte c = (-1)^(popcount(i & c) + i_4 h) as int8.  For c = 4 d + e,
+  // popcount(i & c) = popcount(i & 4d) + popcount(i & e): dword d is the
+  // pattern of e = 0 .. 3 with every byte negated where parity(i & 4d)
+  // (negation of +-1 bytes: XOR 0xFE)
+  const uint32_t par_e = ((i & 1u) ? 0x0000FF00u | 0xFF000000u : 0u) ^
+                         ((i & 2u) ? 0x00FF0000u | 0xFF000000u : 0u);
+  const uint32_t flip = ((i >> 4) & h) ? 0xFEFEFEFEu : 0u;
+  const uint32_t w0 = (0x01010101u ^ (par_e & 0xFEFEFEFEu)) ^ flip;
+  const uint32_t m2 = (i & 4u) ? 0xFEFEFEFEu : 0u, m3 = (i & 8u) ? 0xFEFEFEFEu : 0u;
+  const i32x4 A0 = {(int)w0, (int)(w0 ^ m2), (int)(w0 ^ m3), (int)(w0 ^ m2 ^ m3)};
+  const i32x4 An = A0 ^ (int)0xFEFEFEFEu;
+  u16x2 kmax = {0, 0};
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    i32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_popcount(mt & t) & 1 ? An : A0, B[t],
+                                                  acc, 0, 0, 0);
+    // H'(0) = H(0) - 64 MULT (u = 0: tile 0, register 0 of the lower half)
+    if (mt == 0) acc[0] -= h ? 0 : 64 * MULT;
+    // registers v and v + 4 (u and u + 8) as one 16-bit pair; the keys carry
+    // 127 - u with the half's 4 h left out (dropped from the maximum below)
+#pragma unroll
+    for (int rb = 0; rb < 4; rb += 2)
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri) {
+        const int v = 4 * rb + ri;
+        const uint32_t ulo = 32 * mt + 8 * rb + ri, uhi = ulo + 8;
+        const s16x2 hv =
+            __builtin_bit_cast(s16x2, __builtin_amdgcn_perm((uint32_t)acc[v + 4], (uint32_t)acc[v], 0x05040100u));
+        const uint32_t idx = (127u - ulo) << 1 | (127u - uhi) << 17;
+        const s16x2 zero = {0, 0};
+        const s16x2 neg = zero - hv;
+        const s16x2 mag = __builtin_elementwise_max(hv, neg);
+        const u16x2 sg = __builtin_bit_cast(u16x2, neg) >> (unsigned short)15;  // [H' > 0]
+        const uint32_t mw = __builtin_bit_cast(uint32_t, mag);
+        const uint32_t hiw = MULT == 3 ? mw << 8 : (mw << 7) & 0xFF00FF00u;
+        const uint32_t key = hiw | __builtin_bit_cast(uint32_t, sg) | idx;
+        kmax = __builtin_elementwise_max(kmax, __builtin_bit_cast(u16x2, key));
+      }
+  }
+  const uint32_t mine = (kmax.x > kmax.y ? kmax.x : kmax.y) - 8u * h;
   const Halves both = halves(mine);
   const uint32_t best = both.lo > both.hi ? both.lo : both.hi;
   return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
@@ -1018,7 +1132,7 @@ __device__ __forceinline__ void symbols(const SegDev &sg, uint32_t item0, int nt
         const uint32_t *blk = lds + L::block(q, b);
         uint32_t sbyte;
         if constexpr (G::PAIR_RM)
-          sbyte = rm_decode_pair<G::MULT>(blk);
+          sbyte = kMfmaRm ? rm_decode_mfma<G::MULT>(blk) : rm_decode_pair<G::MULT>(blk);
         else
           sbyte = rm_decode_block<G::MULT>(blk);
         if (fl < avail && lane < BPP) lds8[L::sym(row0 + g0 + q, b)] = (uint8_t)sbyte;
