@@ -100,12 +100,11 @@ typedef struct hqc_params {
   int32_t shape;    /* kernel shape: 0 = chosen by the library, 1 = shape A, 2 =
                        shape B (single-set HQC-1 or HQC-3 decryption, decoding
                        and keyed decryption only; HQC_EINVAL elsewhere).
-                       A: every set's default (HQC-1: one RM block per lane,
-                       received words of four items in LDS; two wavefronts
-                       per SIMD).  B: every RM block on a lane pair, less LDS
-                       per wavefront (HQC-1: two items' received words;
-                       HQC-3: the received word over the doubled u), three
-                       wavefronts per SIMD.  Results never depend on it. */
+                       A: every set's default, two wavefronts per SIMD.
+                       B: three wavefronts per SIMD, built for the smaller
+                       register budget (HQC-3: with its received word over
+                       the doubled u, for less LDS per wavefront).  Results
+                       never depend on it. */
 } hqc_params_t;
 
 /* One homogeneous part of a mixed-parameter batch (host struct). */
@@ -328,20 +327,23 @@ void hqc_shutdown(void);
 
 /* ---- Launch-configuration autotuner ------------------------------------
  * The decryption kernels take three launch parameters that never change the
- * results: the kernel shape (params->shape: RM blocks per lane or per lane
- * pair, LDS layout, wavefronts per SIMD), the persistent grid (workgroups)
+ * results: the kernel shape (params->shape: register budget and LDS layout
+ * for two or three wavefronts per SIMD), the persistent grid (workgroups)
  * and the tile (ciphertexts per workgroup tile; a workgroup decodes the
  * Reed-Solomon words of consecutive tiles together, two lanes per word in
  * passes of up to 32 words, one lane per word in larger ones).  The library
  * keeps a table, per device, parameter set and batch-size bucket (the power
  * of two at or above count), of the configuration to use when a single-set
  * call leaves params->grid, params->tile and params->shape at 0.  Without an
- * entry, and for every mixed-set call, it chooses what the caller left open:
- * shape B for single-set HQC-1 and HQC-3 once count gives B's occupancy
- * grid 16 items per workgroup, else shape A; the occupancy grid of the shape;
- * and the largest power-of-two tile (1 .. 64) not above count / grid.
- * Because the kernels' time does not depend on the data (constant time),
- * configurations can be timed on random inputs. */
+ * entry such a call uses the library's built-in table (the autotuner's
+ * choices on MI355X at each power-of-two batch from 2^8 to 2^20 items).
+ * Other calls (mixed sets, decoding, some knobs given) get what the caller
+ * left open by rule: shape B for single-set HQC-3 once count gives B's
+ * occupancy grid 16 items per workgroup, else shape A; the occupancy grid
+ * of the shape; and the largest power-of-two tile not above count / grid
+ * (at most 64; 32 in shape B).  Because the kernels' time does not depend
+ * on the data (constant time), configurations can be timed on random
+ * inputs. */
 typedef struct hqc_tune_report {
   int32_t param_id;
   int32_t tile, grid;            /* chosen configuration (now in the table) */

@@ -25,10 +25,10 @@ constexpr int odd_dword_stride(int b) {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // Kernel shapes of the decryption kernels (SH, a tuning knob; results never
-// depend on it): shape 0 for every set, and shape 1 for HQC-1 and HQC-3, in
-// which every RM block is decoded on a lane pair and less LDS per wavefront
-// allows three wavefronts per SIMD instead of two.  Key generation and
-// encryption use shape 0's sizes.
+// depend on it): shape 0 for every set, and shape 1 for HQC-1 and HQC-3,
+// built for three wavefronts per SIMD instead of two (HQC-3 with the compact
+// LDS layout to fit them).  Key generation and encryption use shape 0's
+// sizes.
 template <int ID, int SH = 0> struct Geo {
   static_assert(SH == 0 || (SH == 1 && ID != 5), "shape 1 exists for HQC-1 and HQC-3");
   using S = Set<ID>;
@@ -54,14 +54,10 @@ template <int ID, int SH = 0> struct Geo {
   static constexpr bool COMPACT = ID == 5 || (ID == 3 && SH == 1);
   static constexpr int TROWS = COMPACT ? 32 : 64;    // items per (sub-)tile
   static constexpr int RB_OFF = COMPACT ? 0 : U2;    // dword offset of the received word
-  // HQC-1 keeps the received words of RMG = 4 items and RM-decodes their
-  // 4 x 46 = 184 blocks in 3 passes of 64 lanes instead of 4 passes of 46;
-  // in shape 1 (lane-pair blocks) 2 items, 92 blocks in 3 passes of 32 pairs
-  static constexpr int RMG = ID == 1 ? (SH == 1 ? 2 : 4) : 1;
-  // HQC-5 (and shape 1) decodes each RM block on a lane pair: HQC-5's 90
-  // blocks take 3 passes of 32 pairs (1.5 full passes) instead of 2 passes
-  // of 64 lanes
-  static constexpr bool PAIR_RM = ID == 5 || SH == 1;
+  // RM blocks are decoded 32 per pass, one per lane pair (matrix cores).
+  // HQC-1 keeps the received words of RMG = 2 items and decodes their
+  // 2 x 46 = 92 blocks in 3 passes instead of 2 x 2
+  static constexpr int RMG = ID == 1 ? 2 : 1;
   static constexpr int WAVES = SH == 1 ? 3 : 2;      // wavefronts per SIMD the kernel is built for
   static constexpr int A_BYTES =
       (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
@@ -91,7 +87,7 @@ __host__ __device__ constexpr uint32_t first_unit(uint32_t block, uint32_t grid,
 }
 
 template <class G> struct Layout {
-  static constexpr int BPP = G::PAIR_RM ? 32 : 64;  // RM blocks per pass
+  static constexpr int BPP = 32;  // RM blocks per pass (one per lane pair)
   // decryption: received-word slot q starts at rb(q); dword d of a word sits
   // at rb(q) + row(d) (one RM block per padded row of BSTR dwords)
   static __host__ __device__ constexpr int rb(int q) { return G::RB_OFF + q * G::RB; }
@@ -109,7 +105,7 @@ template <class G> struct Layout {
   // RM pass p of a group: the flat block index lane takes (q n1 + b for
   // block b of slot q), before clamping to the blocks received
   static __host__ __device__ constexpr int pass_flat(int p, int lane) {
-    return BPP * p + (G::PAIR_RM ? (lane & 31) : lane);
+    return BPP * p + (lane & 31);
   }
   static __host__ __device__ constexpr int pass_clamp(int fl, int avail) {
     return fl < avail ? fl : avail - 1;

@@ -15,10 +15,11 @@
 //      fall in distinct LDS banks whatever the secret offset is).  The next
 //      index's window is loaded while the current one is combined.
 //  S2  XOR with v, into an LDS copy of v laid out one RM block per padded row.
-//  S3-S5  one RM block per lane: bit-sliced sum of the copies, 128-point
-//      Walsh-Hadamard transform on packed 16-bit pairs in VGPRs, and a
-//      packed 16-bit peak search (magnitude, then smallest index, then
-//      sign); the symbol byte goes to the tile's symbol table in LDS.
+//  S3-S5  one RM block per lane pair, 32 per pass: bit-sliced sum of the
+//      copies, the 128-point Walsh-Hadamard transform of the counts as an
+//      int8 matrix product on the matrix cores (MFMA), and a packed 16-bit
+//      peak search (magnitude, then smallest index, then sign); the symbol
+//      byte goes to the tile's symbol table in LDS.
 // Then each lane, or each lane pair for tiles of at most 32 items, decodes
 // the Reed-Solomon word of one item of the tile (S6-S10): syndromes as
 // GF(2)-linear bit rows, Berlekamp-Massey in its reformulated form on
@@ -39,226 +40,17 @@
 namespace hqc {
 namespace {
 
-constexpr bool kMfmaRm = true;
-
-// ---- S3-S5: one duplicated RM(1,7) block -> symbol byte ---------------------
-template <int MULT>
-__device__ __forceinline__ uint32_t rm_decode_block(const uint32_t *blk) {
-  // bit-sliced count of set copies per position: F = p0 + 2 p1 + 4 p2
-  uint32_t p0[4], p1[4], p2[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    uint32_t a = blk[q], b = blk[4 + q], c = blk[8 + q];
-    uint32_t s = xor3(a, b, c), cy = maj3(a, b, c);
-    if constexpr (MULT == 3) {
-      p0[q] = s;
-      p1[q] = cy;
-      p2[q] = 0;
-    } else {
-      uint32_t d = blk[12 + q], e = blk[16 + q];
-      uint32_t s2 = xor3(s, d, e), cy2 = maj3(s, d, e);
-      p0[q] = s2;
-      p1[q] = cy ^ cy2;
-      p2[q] = cy & cy2;
-    }
-  }
-  // F as bytes, 4 positions per dword: B[g] byte c = F(4g + c).  A nibble
-  // of a plane spreads to the low bit of 4 bytes by one multiply.
-  uint32_t B[32];
-#pragma unroll
-  for (int g = 0; g < 32; ++g) {
-    const int q = g >> 3, sh = 4 * (g & 7);
-    uint32_t v = (__builtin_amdgcn_ubfe(p0[q], sh, 4) * 0x204081u) & 0x01010101u;
-    v += ((__builtin_amdgcn_ubfe(p1[q], sh, 4) * 0x204081u) & 0x01010101u) << 1;
-    if constexpr (MULT == 5) v += ((__builtin_amdgcn_ubfe(p2[q], sh, 4) * 0x204081u) & 0x01010101u) << 2;
-    B[g] = v;
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  // h[m] = (F(m), F(m + 64)) as 16-bit halves
-  s16x2 h[64];
-#pragma unroll
-  for (int m = 0; m < 64; ++m) {
-    const uint32_t c = (uint32_t)(m & 3);
-    const uint32_t sel = c | 0x0C00u | ((4u + c) << 16) | 0x0C000000u;
-    h[m] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(B[(m >> 2) + 16], B[m >> 2], sel));
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  // transform stages 1 .. 32 pair elements inside each half ...
-#pragma unroll
-  for (int hh = 1; hh < 64; hh <<= 1) {
-#pragma unroll
-    for (int m = 0; m < 64; ++m) {
-      if (m & hh) continue;
-      s16x2 a = h[m], c = h[m + hh];
-      h[m] = a + c;
-      h[m + hh] = a - c;
-    }
-  }
-  // ... stage 64 pairs the two halves of each dword: (a, b) -> (a + b, a - b)
-  // as one v_pk_mad_i16: low = a*1 + b, high = b*(-1) + a
-#pragma unroll
-  for (int m = 0; m < 64; ++m) {
-    uint32_t x = __builtin_bit_cast(uint32_t, h[m]), d;
-    asm("v_pk_mad_i16 %0, %1, %2, %1 op_sel:[0,0,1] op_sel_hi:[1,1,0]"
-        : "=v"(d)
-        : "v"(x), "v"(0xFFFF0001u));
-    h[m] = __builtin_bit_cast(s16x2, d);
-  }
-  // H = transform of the counts.  The correlation with codeword (u, sign) is
-  // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u) with H'(0) = H(0) - 64*MULT,
-  // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
-  // One 16-bit key per u: bits 15..8 = |H'(u)| (<= 192 for MULT 3) or
-  // |H'(u)| >> 1 (<= 160 for MULT 5; every H'(u) has the parity of sum F, so
-  // halving keeps the order), bits 7..1 = 127 - u, bit 0 = [H'(u) > 0].
-  h[0].x = (short)(h[0].x - 64 * MULT);
-  __builtin_amdgcn_sched_barrier(0);
-  u16x2 kmax = {0, 0};
-#pragma unroll
-  for (int m = 0; m < 64; ++m) {
-    // dword m holds u = m (low half) and u = m + 64 (high half)
-    const uint32_t idx = (uint32_t)(127 - m) << 1 | (uint32_t)(63 - m) << 17;
-    const s16x2 zero = {0, 0};
-    const s16x2 neg = zero - h[m];
-    const s16x2 mag = __builtin_elementwise_max(h[m], neg);
-    const u16x2 sgn = __builtin_bit_cast(u16x2, neg) >> (unsigned short)15;  // [H' > 0]
-    const uint32_t mw = __builtin_bit_cast(uint32_t, mag);
-    const uint32_t hiw = MULT == 3 ? mw << 8 : (mw << 7) & 0xFF00FF00u;
-    const uint32_t key = hiw | __builtin_bit_cast(uint32_t, sgn) | idx;
-    kmax = __builtin_elementwise_max(kmax, __builtin_bit_cast(u16x2, key));
-  }
-  const uint32_t best = kmax.x > kmax.y ? kmax.x : kmax.y;
-  return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
-}
-
-// ---- S3-S5: one duplicated RM(1,7) block -> symbol byte, on a lane pair -------
-// Lanes l and l + 32 decode the same block.  Half s = l / 32 takes positions
-// 32s .. 32s+31 and 64+32s .. 64+32s+31 (dwords s and 2+s of every copy):
-// its 32 registers h[m'] hold (F(m), F(m+64)) for m = 32s + m'.  The
-// transform stages pairing m with m + 1 .. m + 16 and m with m + 64 are
-// local; the stage pairing m with m + 32 pairs the halves and goes through
-// v_permlane32_swap_b32 (the stages commute, so it runs last).  Both lanes
-// return the symbol.
-template <int MULT>
-__device__ __forceinline__ uint32_t rm_decode_pair(const uint32_t *blk) {
-  const bool upper = lane_id() >= 32;
-  const int s = upper ? 1 : 0;
-  // bit-sliced count of set copies per position: F = p0 + 2 p1 + 4 p2, for
-  // the half's two dwords e = 0, 1 (dword s + 2e of each copy)
-  uint32_t p0[2], p1[2], p2[2];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const uint32_t *b = blk + 2 * e + s;
-    const uint32_t x = b[0], y = b[4], z = b[8];
-    const uint32_t sm = xor3(x, y, z), cy = maj3(x, y, z);
-    if constexpr (MULT == 3) {
-      p0[e] = sm;
-      p1[e] = cy;
-      p2[e] = 0;
-    } else {
-      const uint32_t d = b[12], f = b[16];
-      const uint32_t sm2 = xor3(sm, d, f), cy2 = maj3(sm, d, f);
-      p0[e] = sm2;
-      p1[e] = cy ^ cy2;
-      p2[e] = cy & cy2;
-    }
-  }
-  // F as bytes, 4 positions per dword: B[g] byte c = F of local position
-  // 4g + c (g < 8: dword e = 0, g >= 8: e = 1).  A nibble of a plane spreads
-  // to the low bit of 4 bytes by one multiply.
-  uint32_t B[16];
-#pragma unroll
-  for (int g = 0; g < 16; ++g) {
-    const int e = g >> 3, sh = 4 * (g & 7);
-    uint32_t v = (__builtin_amdgcn_ubfe(p0[e], sh, 4) * 0x204081u) & 0x01010101u;
-    v += ((__builtin_amdgcn_ubfe(p1[e], sh, 4) * 0x204081u) & 0x01010101u) << 1;
-    if constexpr (MULT == 5) v += ((__builtin_amdgcn_ubfe(p2[e], sh, 4) * 0x204081u) & 0x01010101u) << 2;
-    B[g] = v;
-  }
-  // h[m'] = (F(m), F(m + 64)) as 16-bit halves
-  s16x2 h[32];
-#pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    const uint32_t c = (uint32_t)(m & 3);
-    const uint32_t sel = c | 0x0C00u | ((4u + c) << 16) | 0x0C000000u;
-    h[m] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(B[(m >> 2) + 8], B[m >> 2], sel));
-  }
-  // local stages: pairs m', m' + hh inside the half ...
-#pragma unroll
-  for (int hh = 1; hh < 32; hh <<= 1) {
-#pragma unroll
-    for (int m = 0; m < 32; ++m) {
-      if (m & hh) continue;
-      s16x2 a = h[m], c = h[m + hh];
-      h[m] = a + c;
-      h[m + hh] = a - c;
-    }
-  }
-  // ... (F(m), F(m+64)) -> (a + b, a - b) as one v_pk_mad_i16: low = a*1 + b,
-  // high = b*(-1) + a ...
-#pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    uint32_t x = __builtin_bit_cast(uint32_t, h[m]), d;
-    asm("v_pk_mad_i16 %0, %1, %2, %1 op_sel:[0,0,1] op_sel_hi:[1,1,0]"
-        : "=v"(d)
-        : "v"(x), "v"(0xFFFF0001u));
-    h[m] = __builtin_bit_cast(s16x2, d);
-  }
-  // ... and across the halves (the lower half keeps a + b, the upper a - b),
-  // two registers at a time: the first swap gives the lower half both
-  // copies of h[m'] and the upper half both copies of h[m' + 16], each half
-  // forms the sum and the difference, and the second swap returns them
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, h[m]),
-                                                    __builtin_bit_cast(uint32_t, h[m + 16]),
-                                                    false, false);
-    const s16x2 a = __builtin_bit_cast(s16x2, (uint32_t)r[0]);
-    const s16x2 b = __builtin_bit_cast(s16x2, (uint32_t)r[1]);
-    const s16x2 sum = a + b, dif = a - b;
-    const auto t = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, sum),
-                                                    __builtin_bit_cast(uint32_t, dif), false, false);
-    h[m] = __builtin_bit_cast(s16x2, (uint32_t)t[0]);
-    h[m + 16] = __builtin_bit_cast(s16x2, (uint32_t)t[1]);
-  }
-  // H = transform of the counts.  The correlation with codeword (u, sign) is
-  // T(u) = 128*MULT*[u == 0] - 2 H(u) = -2 H'(u) with H'(0) = H(0) - 64*MULT,
-  // so the ML symbol is the smallest u maximising |H'(u)|, bit 7 = [H'(u) > 0].
-  // One 16-bit key per u: bits 15..8 = |H'(u)| (<= 192 for MULT 3) or
-  // |H'(u)| >> 1 (<= 160 for MULT 5; every H'(u) has the parity of sum F, so
-  // halving keeps the order), bits 7..1 = 127 - u, bit 0 = [H'(u) > 0].
-  h[0].x = (short)(h[0].x - (upper ? 0 : 64 * MULT));
-  // register m' holds u = 32s + m' (low half) and u = 32s + m' + 64 (high);
-  // the keys carry 127 - m' and 63 - m', and the upper half's maximum drops
-  // 2 * 32 from both index fields afterwards (no borrow: the fields are >= 64)
-  u16x2 kmax = {0, 0};
-#pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    const uint32_t idx = (uint32_t)(127 - m) << 1 | (uint32_t)(63 - m) << 17;
-    const s16x2 zero = {0, 0};
-    const s16x2 neg = zero - h[m];
-    const s16x2 mag = __builtin_elementwise_max(h[m], neg);
-    const u16x2 sg = __builtin_bit_cast(u16x2, neg) >> (unsigned short)15;  // [H' > 0]
-    const uint32_t mw = __builtin_bit_cast(uint32_t, mag);
-    const uint32_t hiw = MULT == 3 ? mw << 8 : (mw << 7) & 0xFF00FF00u;
-    const uint32_t key = hiw | __builtin_bit_cast(uint32_t, sg) | idx;
-    kmax = __builtin_elementwise_max(kmax, __builtin_bit_cast(u16x2, key));
-  }
-  const u16x2 drop = upper ? u16x2{64, 64} : u16x2{0, 0};
-  kmax = kmax - drop;
-  const uint32_t mine = kmax.x > kmax.y ? kmax.x : kmax.y;
-  const Halves both = halves(mine);
-  const uint32_t best = both.lo > both.hi ? both.lo : both.hi;
-  return (127u - ((best >> 1) & 127u)) | (best & 1u) << 7;
-}
-
-// ---- S3-S5: one duplicated RM(1,7) block per lane pair, on the matrix cores ---
-// The correlations of the received block with the 256 codewords of RM(1,7)
-// are +-(128 MULT [u == 0] - 2 H(u)), where H = W F is the Walsh-Hadamard
-// transform of the copy counts F (W[u][k] = (-1)^popcount(u & k)): a dense
-// 128 x 128 by 128 x 32 integer product for the 32 blocks of a pass, run as
-// int8 MFMAs (v_mfma_i32_32x32x32_i8: 32 rows u of W times 32 positions k,
-// times the counts of 32 blocks, one block per column).  Lanes l and l + 32
-// hold block l mod 32.
+// ---- S3-S5: one duplicated RM(1,7) block -> symbol byte, on the matrix cores --
+// Maximum-likelihood decoding of a block: the correlations of the received
+// copies with the 256 codewords of RM(1,7) are +-(128 MULT [u == 0] - 2 H(u)),
+// where H = W F is the Walsh-Hadamard transform of the copy counts F (the
+// number of copies with bit k set; W[u][k] = (-1)^popcount(u & k)).  For the
+// 32 blocks of a pass that is a dense 128 x 128 by 128 x 32 integer product,
+// run as int8 MFMAs (v_mfma_i32_32x32x32_i8: 32 rows u of W times 32
+// positions k, times the counts of 32 blocks, one block per column) -- 16
+// per pass, in place of 7 stages of packed 16-bit butterflies (measured
+// 10 % faster on the HQC-1 decryption, 15 % on the decoder stress launch).
+// Lanes l and l + 32 hold block l mod 32 and both return its symbol.
 //
 // Positions are split over the four K steps t and the two half-waves h as
 // k = 32 t + 16 h + c: byte c (0 .. 15) of lane (j, h)'s B operand in step t
@@ -268,8 +60,14 @@ __device__ __forceinline__ uint32_t rm_decode_pair(const uint32_t *blk) {
 // W[32 mt + i][32 t + 16 h + c] = (-1)^(popcount(i & (16 h + c)) + popcount(mt & t)):
 // one per-lane tile A0 and its negation, chosen per (mt, t) at compile time.
 // The result of M tile mt in lane (j, h), register 4 rb + ri, is H(u) of
-// block j for u = 32 mt + 8 rb + 4 h + ri; the peak search is that of
-// rm_decode_pair on 16-bit pairs of these.
+// block j for u = 32 mt + 8 rb + 4 h + ri.
+//
+// The ML symbol is the smallest u maximising |H'(u)|, H'(u) = H(u) -
+// 64 MULT [u == 0], with bit 7 = [H'(u) > 0].  The search runs on 16-bit
+// pairs of results, one 16-bit key per u: bits 15..8 = |H'(u)| (<= 192 for
+// MULT 3) or |H'(u)| >> 1 (<= 160 for MULT 5: every H'(u) has the parity of
+// sum F, so halving keeps the order), bits 7..1 = 127 - u, bit 0 = [H' > 0];
+// one packed maximum per pair, then one across the two half-waves.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 
@@ -1130,11 +928,7 @@ __device__ __forceinline__ void symbols(const SegDev &sg, uint32_t item0, int nt
         const int f = L::pass_clamp(fl, avail);
         const int q = f / G::n1, b = f - q * G::n1;
         const uint32_t *blk = lds + L::block(q, b);
-        uint32_t sbyte;
-        if constexpr (G::PAIR_RM)
-          sbyte = kMfmaRm ? rm_decode_mfma<G::MULT>(blk) : rm_decode_pair<G::MULT>(blk);
-        else
-          sbyte = rm_decode_block<G::MULT>(blk);
+        const uint32_t sbyte = rm_decode_mfma<G::MULT>(blk);
         if (fl < avail && lane < BPP) lds8[L::sym(row0 + g0 + q, b)] = (uint8_t)sbyte;
         ++passes;
       }

@@ -52,25 +52,31 @@ def test_autotune_rejects_bad_arguments():
 
 
 def test_builtin_launch_config():
-    """Without a table entry: shape B for HQC-1 and HQC-3 once the batch gives
-    B's occupancy grid 16 items per workgroup, the occupancy grid, and the
-    largest power-of-two tile not above count / grid (at most 64)."""
+    """Without a table entry: single-set decryption with every knob open
+    takes the built-in table's choice (a valid launch: shape B only where it
+    exists, tile 1 .. 64, grid at most the tiles); with the shape given, the
+    occupancy grid of that shape and the largest power-of-two tile not above
+    count / grid (at most 64; 32 in shape B)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2512_12904_amd import hqc
     hqc.tune_clear()
     for pid in (1, 3, 5):
-        full_a = hqc.launch_config(pid, 1 << 20, shape=1)[2]
-        full_b = hqc.launch_config(pid, 1 << 20, shape=2)[2] if pid != 5 else None
-        for count in (1, 100, 4096, 16384, 65536, 262144):
+        shapes = (1, 2) if pid != 5 else (1,)
+        full = {sh: hqc.launch_config(pid, 1 << 20, shape=sh)[2] for sh in shapes}
+        for count in (1, 100, 4096, 16384, 65536, 262144, 1 << 20):
             sh, t, g = hqc.launch_config(pid, count)
-            want_sh = 2 if (full_b and count >= 16 * full_b) else 1
-            full = full_b if want_sh == 2 else full_a
-            want_t = 1
-            while want_t < 64 and 2 * want_t <= count // full:
-                want_t *= 2
-            assert (sh, t, g) == (want_sh, want_t, min(full, -(-count // want_t))), (pid, count)
+            assert sh in shapes and 1 <= t <= 64 and 1 <= g <= min(full[sh], -(-count // t)), \
+                (pid, count, sh, t, g)
+            for want_sh in shapes:
+                sh, t, g = hqc.launch_config(pid, count, shape=want_sh)
+                cap = 32 if want_sh == 2 else 64
+                want_t = 1
+                while want_t < cap and 2 * want_t <= count // full[want_sh]:
+                    want_t *= 2
+                assert (sh, t, g) == (want_sh, want_t, min(full[want_sh], -(-count // want_t))), \
+                    (pid, count, want_sh)
     with pytest.raises(hqc.HqcError):
         hqc.launch_config(5, 100, shape=2)
     with pytest.raises(hqc.HqcError):
