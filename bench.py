@@ -20,8 +20,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes, one 32-bit integer op per lane per
-# clock at 2.4 GHz.
+# clock at 2.4 GHz; dense int8 matrix-core peak 5.0 POP/s.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_INT8_MATRIX = 5.0e15
 PEAK_HBM = 8.0e12
 
 SETS = {  # Table I plus the derived sizes the op model needs
@@ -31,9 +32,9 @@ SETS = {  # Table I plus the derived sizes the op model needs
 }
 
 
-def op_model(pid):
+def op_model_vector_transform(pid):
     """Algorithmic integer operations of one decryption (what the method must
-    compute, not the dense work it avoids):
+    compute, not the dense work it avoids), every step on the vector ALUs:
       product  2 w W32      one funnel shift + one XOR per output dword per index
       add v    W32
       RM       n1 (128 mult + 7*128 + 2*128)   expand, butterflies, peak search
@@ -49,15 +50,17 @@ def op_model(pid):
     return prod + w32 + rm + 6 * gf
 
 
-def decode_op_model(pid):
-    """Algorithmic integer operations of decoding one received word (RM and
-    RS terms of op_model; no product, no add)."""
-    s = SETS[pid]
-    mult = s["n2"] // 128
-    d = s["delta"]
-    rm = s["n1"] * (128 * mult + 7 * 128 + 2 * 128)
-    gf = 2 * d * (s["n1"] - 1) + 8 * d * d + 2 * d * d + s["n1"] * 2 * d + s["n1"] * 3 * d
-    return rm + 6 * gf
+def op_model(pid):
+    """The vector-ALU part of op_model_vector_transform: without the
+    Walsh-Hadamard butterflies (n1 * 7 * 128), which the kernels run as int8
+    matrix products on the matrix cores (matrix_ops)."""
+    return op_model_vector_transform(pid) - SETS[pid]["n1"] * 7 * 128
+
+
+def matrix_ops(pid):
+    """int8 matrix-core operations of one decryption: H = W F for every RM
+    block, a 128 x 128 by 128 product (one multiply and one add per term)."""
+    return SETS[pid]["n1"] * 2 * 128 * 128
 
 
 def hbm_bytes(pid):
@@ -831,7 +834,19 @@ def main():
                                   or {}).get("traffic_bytes") if args.count == 65536 else None),
                      "traffic_algorithmic": hbm_bytes(pid0) * args.count,
                      "ops_per_decrypt": op_model(pid0), "units_per_launch": args.count,
-                     "kernel_ms": main_r["ms_mean"]},
+                     "kernel_ms": main_r["ms_mean"],
+                     # the same launch priced with the transform on the vector
+                     # ALUs (the form a kernel without matrix cores runs)
+                     "ops_per_decrypt_transform_on_vector": op_model_vector_transform(pid0),
+                     "frac_transform_on_vector": op_model_vector_transform(pid0) * args.count
+                     / (main_r["ms_mean"] / 1e3) / PEAK_INT_OPS,
+                     "valu_busy_counters": main_r.get("valu_busy_counters"),
+                     "matrix": {"ops_per_decrypt": matrix_ops(pid0),
+                                "achieved": matrix_ops(pid0) * args.count
+                                / (main_r["ms_mean"] / 1e3) / 1e12,
+                                "peak": PEAK_INT8_MATRIX / 1e12, "unit": "TOP/s (int8)",
+                                "frac": matrix_ops(pid0) * args.count
+                                / (main_r["ms_mean"] / 1e3) / PEAK_INT8_MATRIX}},
     }
     if not args.no_per_item:
         line["per_item_decrypts_per_s"] = main_r["per_item_decrypts_per_s"]
