@@ -508,7 +508,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(seconds_target=12.0):
+def cpu_baseline(seconds_target=20.0):
     """The CPU checker (oracle/) on the host cores: honest HQC-1 ciphertexts
     made by the checker itself, decryption timed over a bounded sample: the
     median of three runs on all threads, and one single-thread run."""
