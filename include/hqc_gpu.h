@@ -341,7 +341,7 @@ void hqc_shutdown(void);
  * left open by rule: shape B for single-set HQC-3 once count gives B's
  * occupancy grid 16 items per workgroup, else shape A; the occupancy grid
  * of the shape; and the largest power-of-two tile not above count / grid
- * (at most 64; 32 in shape B).  Because the kernels' time does not depend
+ * (at most 64).  Because the kernels' time does not depend
  * on the data (constant time), configurations can be timed on random
  * inputs. */
 typedef struct hqc_tune_report {
@@ -360,9 +360,10 @@ typedef struct hqc_tune_report {
 /* Times candidate (shape, tile, grid) triples of the decryption kernel for param_id
  * (1, 3 or 5) on count random ciphertexts (count in 1 .. 2^20): one untimed
  * launch each, whose messages must all be byte-identical, then reps rounds
- * that time every candidate once, on `stream` (NULL: null stream).  The
- * candidate with the lowest median is stored in the table if it beats the
- * built-in default by more than 1 %, else the default is (nothing is
+ * that time every candidate once (four back-to-back launches per sample),
+ * on `stream` (NULL: null stream).  The candidate with the lowest median
+ * per launch is stored in the table if it beats the built-in default by
+ * more than 1 %, else the default is (nothing is
  * stored if any candidate's messages differed: out->identical = 0); *out
  * gets the choice and both medians.  Allocates and frees its own device buffers
  * (u, v, y, m: count * (8 u_words + 8 v_words + 4 w + k) bytes); blocks

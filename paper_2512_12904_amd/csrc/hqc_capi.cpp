@@ -369,10 +369,10 @@ int occupancy_grid(int op, unsigned mask, int shape, int *out) {
 }
 
 // The library's built-in launches of single-set decryption on MI355X: the
-// autotuner's choices (hqc_autotune_decrypt, 9 timing rounds, every
-// candidate's messages identical) at each power-of-two batch from 2^8 to
-// 2^20 items: shape (1 = A, 2 = B), tile, and the grid in workgroups per
-// compute unit.  A batch uses the entry of its bucket (the power of two at
+// autotuner's choices (hqc_autotune_decrypt, 7 timing rounds of four
+// back-to-back launches, every candidate's messages identical) at each
+// power-of-two batch from 2^8 to 2^20 items: shape (1 = A, 2 = B), tile,
+// and the grid in workgroups per compute unit.  A batch uses the entry of its bucket (the power of two at
 // or above its size; 2^8 below, 2^20 above).
 struct BuiltinEntry {
   uint8_t shape, tile, wg_per_cu;
@@ -380,14 +380,14 @@ struct BuiltinEntry {
 constexpr int kBuiltinLo = 8, kBuiltinHi = 20;
 constexpr BuiltinEntry kBuiltin[3][kBuiltinHi - kBuiltinLo + 1] = {
     // HQC-1
-    {{1, 1, 1}, {1, 1, 12}, {1, 1, 12}, {1, 2, 4}, {1, 4, 4}, {1, 4, 6}, {1, 4, 12},
-     {1, 8, 12}, {1, 16, 12}, {1, 32, 12}, {1, 64, 12}, {1, 64, 12}, {2, 64, 12}},
+    {{1, 1, 1}, {1, 1, 12}, {1, 1, 12}, {1, 2, 4}, {1, 4, 4}, {1, 4, 6}, {2, 4, 12},
+     {2, 8, 12}, {2, 16, 12}, {2, 32, 12}, {2, 32, 12}, {2, 64, 12}, {2, 64, 12}},
     // HQC-3
-    {{1, 1, 8}, {1, 1, 8}, {1, 1, 4}, {1, 1, 4}, {2, 1, 6}, {1, 4, 8}, {1, 4, 8},
-     {2, 8, 12}, {2, 8, 12}, {2, 32, 12}, {2, 32, 12}, {1, 40, 8}, {1, 64, 8}},
+    {{2, 1, 1}, {2, 1, 2}, {2, 1, 4}, {2, 2, 4}, {1, 2, 8}, {1, 2, 8}, {2, 4, 12},
+     {2, 4, 12}, {2, 16, 12}, {2, 16, 12}, {2, 64, 12}, {2, 64, 12}, {1, 64, 8}},
     // HQC-5
-    {{1, 1, 8}, {1, 1, 8}, {1, 1, 8}, {1, 1, 4}, {1, 4, 4}, {1, 2, 6}, {1, 4, 8},
-     {1, 8, 8}, {1, 1, 8}, {1, 32, 10}, {1, 64, 8}, {1, 64, 8}, {1, 64, 8}},
+    {{1, 1, 8}, {1, 1, 8}, {1, 1, 8}, {1, 1, 4}, {1, 2, 8}, {1, 4, 8}, {1, 8, 8},
+     {1, 2, 8}, {1, 16, 8}, {1, 32, 8}, {1, 64, 8}, {1, 64, 8}, {1, 64, 8}},
 };
 
 // The built-in launch of `items` items; only what the caller left open is
@@ -397,9 +397,7 @@ constexpr BuiltinEntry kBuiltin[3][kBuiltinHi - kBuiltinLo + 1] = {
 //  * otherwise shape 1 (three wavefronts per SIMD) for single-set HQC-3
 //    once the batch gives its occupancy grid tiles of 16 items, else shape
 //    0; the occupancy grid; and the largest power-of-two tile not above
-//    items / grid, at most 64 (32 in shape 1, whose one-lane Reed-Solomon
-//    form for larger tiles measured slower: 262,144 HQC-3 items 3.40 ms at
-//    64 against 2.82 at 32).
+//    items / grid, at most 64.
 int builtin_launch(int op, unsigned mask, uint64_t items, int *shape, uint32_t *tile,
                    int *grid) {
   const int set = mask == 1u ? 0 : mask == 2u ? 1 : mask == 4u ? 2 : -1;
@@ -436,9 +434,8 @@ int builtin_launch(int op, unsigned mask, uint64_t items, int *shape, uint32_t *
   }
   if (*tile == 0) {
     const uint64_t per = items / (uint64_t)*grid;
-    const uint32_t cap = *shape == 1 ? 32 : 64;
     uint32_t t = 1;
-    while (t < cap && 2ull * t <= per) t *= 2;
+    while (t < 64 && 2ull * t <= per) t *= 2;
     *tile = t;
   }
   return HQC_OK;

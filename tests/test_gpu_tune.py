@@ -56,7 +56,7 @@ def test_builtin_launch_config():
     takes the built-in table's choice (a valid launch: shape B only where it
     exists, tile 1 .. 64, grid at most the tiles); with the shape given, the
     occupancy grid of that shape and the largest power-of-two tile not above
-    count / grid (at most 64; 32 in shape B)."""
+    count / grid (at most 64)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -71,9 +71,8 @@ def test_builtin_launch_config():
                 (pid, count, sh, t, g)
             for want_sh in shapes:
                 sh, t, g = hqc.launch_config(pid, count, shape=want_sh)
-                cap = 32 if want_sh == 2 else 64
                 want_t = 1
-                while want_t < cap and 2 * want_t <= count // full[want_sh]:
+                while want_t < 64 and 2 * want_t <= count // full[want_sh]:
                     want_t *= 2
                 assert (sh, t, g) == (want_sh, want_t, min(full[want_sh], -(-count // want_t))), \
                     (pid, count, want_sh)
