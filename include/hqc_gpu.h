@@ -360,10 +360,11 @@ typedef struct hqc_tune_report {
 /* Times candidate (shape, tile, grid) triples of the decryption kernel for param_id
  * (1, 3 or 5) on count random ciphertexts (count in 1 .. 2^20): one untimed
  * launch each, whose messages must all be byte-identical, then reps rounds
- * that time every candidate once (four back-to-back launches per sample),
- * on `stream` (NULL: null stream).  The candidate with the lowest median
- * per launch is stored in the table if it beats the built-in default by
- * more than 1 %, else the default is (nothing is
+ * that time every candidate once, in a freshly shuffled order per round
+ * (each sample four back-to-back hipGraph launches behind two untimed
+ * ones), on `stream` (NULL: null stream).  The candidate with the lowest
+ * median per launch is stored in the table if it beats the built-in default
+ * by more than 1 %, else the default is (nothing is
  * stored if any candidate's messages differed: out->identical = 0); *out
  * gets the choice and both medians.  Allocates and frees its own device buffers
  * (u, v, y, m: count * (8 u_words + 8 v_words + 4 w + k) bytes); blocks

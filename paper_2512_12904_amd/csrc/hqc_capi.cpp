@@ -369,10 +369,10 @@ int occupancy_grid(int op, unsigned mask, int shape, int *out) {
 }
 
 // The library's built-in launches of single-set decryption on MI355X: the
-// autotuner's choices (hqc_autotune_decrypt, 7 timing rounds of four
-// back-to-back launches, every candidate's messages identical) at each
-// power-of-two batch from 2^8 to 2^20 items: shape (1 = A, 2 = B), tile,
-// and the grid in workgroups per compute unit.  A batch uses the entry of its bucket (the power of two at
+// autotuner's choices (hqc_autotune_decrypt: 7 rounds in shuffled order,
+// four back-to-back graph launches per sample, every candidate's messages
+// identical) at each power-of-two batch from 2^8 to 2^20 items: shape
+// (1 = A, 2 = B), tile, and the grid in workgroups per compute unit.  A batch uses the entry of its bucket (the power of two at
 // or above its size; 2^8 below, 2^20 above).
 struct BuiltinEntry {
   uint8_t shape, tile, wg_per_cu;
@@ -380,14 +380,14 @@ struct BuiltinEntry {
 constexpr int kBuiltinLo = 8, kBuiltinHi = 20;
 constexpr BuiltinEntry kBuiltin[3][kBuiltinHi - kBuiltinLo + 1] = {
     // HQC-1
-    {{1, 1, 1}, {1, 1, 12}, {1, 1, 12}, {1, 2, 4}, {1, 4, 4}, {1, 4, 6}, {2, 4, 12},
-     {2, 8, 12}, {2, 16, 12}, {2, 32, 12}, {2, 32, 12}, {2, 64, 12}, {2, 64, 12}},
+    {{1, 1, 1}, {1, 1, 12}, {1, 1, 12}, {1, 2, 4}, {1, 4, 4}, {1, 4, 6}, {1, 2, 12},
+     {2, 8, 12}, {2, 16, 12}, {2, 32, 12}, {1, 64, 12}, {1, 64, 12}, {2, 64, 12}},
     // HQC-3
-    {{2, 1, 1}, {2, 1, 2}, {2, 1, 4}, {2, 2, 4}, {1, 2, 8}, {1, 2, 8}, {2, 4, 12},
-     {2, 4, 12}, {2, 16, 12}, {2, 16, 12}, {2, 64, 12}, {2, 64, 12}, {1, 64, 8}},
+    {{2, 1, 1}, {2, 1, 2}, {2, 1, 4}, {2, 2, 4}, {1, 2, 8}, {1, 4, 8}, {2, 4, 12},
+     {2, 8, 12}, {2, 16, 12}, {2, 16, 12}, {2, 32, 12}, {2, 64, 12}, {1, 64, 8}},
     // HQC-5
-    {{1, 1, 8}, {1, 1, 8}, {1, 1, 8}, {1, 1, 4}, {1, 2, 8}, {1, 4, 8}, {1, 8, 8},
-     {1, 2, 8}, {1, 16, 8}, {1, 32, 8}, {1, 64, 8}, {1, 64, 8}, {1, 64, 8}},
+    {{1, 1, 8}, {1, 1, 2}, {1, 1, 8}, {1, 1, 4}, {1, 2, 8}, {1, 4, 8}, {1, 2, 8},
+     {1, 4, 8}, {1, 16, 8}, {1, 32, 8}, {1, 64, 8}, {1, 64, 8}, {1, 64, 8}},
 };
 
 // The built-in launch of `items` items; only what the caller left open is

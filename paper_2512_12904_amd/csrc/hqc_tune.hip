@@ -7,9 +7,10 @@
 // 1/2 .. 3/2 of that shape's occupancy grid, or one tile per workgroup when
 // a batch has fewer tiles than half that grid.  Each is launched once
 // untimed and its messages compared byte for byte with those of the
-// built-in default; then `reps` rounds time every candidate once per round
-// with HIP events on the caller's stream (so drift during the search hits
-// all alike), and the median decides.  Inputs are random words and random
+// built-in default; then `reps` rounds time every candidate once per round,
+// in a freshly shuffled order, with HIP events on the caller's stream (so
+// drift during the search, and what the previous candidate leaves behind,
+// hit all alike), and the median decides.  Inputs are random words and random
 // support indices: the kernels' time does not depend on the data, so any
 // input is representative.
 #include <hip/hip_runtime.h>
@@ -131,6 +132,7 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
     std::memset(&p, 0, sizeof p);
     p.param_id = param_id;
     p.stream = stream;
+    p.flags = HQC_F_GRAPH;  // the launch mode of batched callers (cached graphs)
     p.tile = cand[c].tile;
     p.grid = cand[c].grid;
     p.shape = cand[c].shape + 1;
@@ -150,12 +152,29 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
     const int rc = hqc_decrypt_batch(&par[0], B.u, B.v, B.y, B.m, count);
     if (rc != HQC_OK) return rc;
   }
-  // each sample is kLaunches back-to-back launches (the steady state of a
-  // busy GPU, not one launch after an idle gap), per launch
+  // each sample is kLaunches back-to-back launches behind two untimed ones
+  // (the steady state of a busy queue, not launches after an idle gap, the
+  // host's argument checks or another candidate), per launch
   constexpr int kLaunches = 4;
   std::vector<std::vector<float>> t(cand.size(), std::vector<float>(reps));
-  for (int r = 0; r < reps; ++r)
-    for (size_t c = 0; c < cand.size(); ++c) {
+  // each round visits the candidates in a fresh order (a seeded shuffle), so
+  // that no candidate always follows the same one: a low-load candidate
+  // (small grid) left the next one's samples about 3 % slow, whichever it was
+  const size_t K = cand.size();
+  std::vector<size_t> order(K);
+  uint64_t rng = 0x5EEDull + (uint64_t)param_id;
+  for (int r = 0; r < reps; ++r) {
+    for (size_t i = 0; i < K; ++i) order[i] = i;
+    for (size_t i = K; i > 1; --i) {
+      rng = rng * 6364136223846793005ull + 1442695040888963407ull;  // Knuth's MMIX LCG
+      std::swap(order[i - 1], order[(size_t)((rng >> 33) % i)]);
+    }
+    for (size_t i = 0; i < K; ++i) {
+      const size_t c = order[i];
+      for (int l = 0; l < 2; ++l) {
+        const int rc = hqc_decrypt_batch(&par[c], B.u, B.v, B.y, B.m, count);
+        if (rc != HQC_OK) return rc;
+      }
       if (hipEventRecord(B.a, st) != hipSuccess) return HQC_EHIP;
       for (int l = 0; l < kLaunches; ++l) {
         const int rc = hqc_decrypt_batch(&par[c], B.u, B.v, B.y, B.m, count);
@@ -166,6 +185,7 @@ extern "C" int hqc_autotune_decrypt(int param_id, size_t count, int reps, void *
         return HQC_EHIP;
       t[c][r] /= (float)kLaunches;
     }
+  }
   std::vector<float> med(cand.size());
   for (size_t c = 0; c < cand.size(); ++c) {
     std::nth_element(t[c].begin(), t[c].begin() + reps / 2, t[c].end());
