@@ -51,18 +51,23 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 struct Grid {
   std::mutex mu;
   std::map<std::tuple<int, int, unsigned, int>, int> cache;  // (device, op, mask, shape) -> grid
+  std::map<int, int> cus;                                    // device -> compute units
 };
 Grid g_grid;
 
-int default_grid(int op, unsigned mask, int *out, int shape = 0) {
+// The occupancy grid (CUs x resident workgroups) of a kernel on the current
+// device, cached per device; *cus_out (optional) gets the CU count.
+int default_grid(int op, unsigned mask, int *out, int shape = 0, int *cus_out = nullptr) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
   std::lock_guard<std::mutex> lk(g_grid.mu);
   auto key = std::make_tuple(dev, op, mask, shape);
   auto it = g_grid.cache.find(key);
-  if (it != g_grid.cache.end()) {
+  auto ct = g_grid.cus.find(dev);
+  if (it != g_grid.cache.end() && ct != g_grid.cus.end()) {
     *out = it->second;
+    if (cus_out) *cus_out = ct->second;
     return HQC_OK;
   }
   int cus = 0, per_cu = 0;
@@ -74,6 +79,8 @@ int default_grid(int op, unsigned mask, int *out, int shape = 0) {
   if (per_cu < 1) per_cu = 1;
   *out = cus * per_cu;
   g_grid.cache[key] = *out;
+  g_grid.cus[dev] = cus;
+  if (cus_out) *cus_out = cus;
   return HQC_OK;
 }
 
@@ -182,16 +189,17 @@ bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid, int *shape) {
   return true;
 }
 
-// Relative time per item of the sets in the shape-A kernels (HQC-1 = 64),
-// from single-set launches on MI355X: decryption (and keyed decryption) of
-// 65,536 items (0.382 / 0.821 / 1.524 ms), decoding of 262,144 words
-// (0.587 / 0.897 / 1.718 ms).
+// Relative time per item of the sets in the shape-A kernels at two
+// wavefronts per SIMD, as in the mixed-set kernels (HQC-1 = 64), from
+// single-set launches on MI355X (grid 2,048): decryption (and keyed
+// decryption) of 65,536 items (0.349 / 0.780 / 1.467 ms), decoding of
+// 262,144 words (0.451 / 0.721 / 1.413 ms).
 uint32_t set_cost(int op, int pid) {
   const bool dec = op == hqc::OP_DECODE;
   switch (pid) {
     case 1: return 64;
-    case 3: return dec ? 98 : 137;
-    case 5: return dec ? 187 : 255;
+    case 3: return dec ? 102 : 143;
+    case 5: return dec ? 201 : 269;
     default: return 64;
   }
 }
@@ -372,8 +380,9 @@ int occupancy_grid(int op, unsigned mask, int shape, int *out) {
 // autotuner's choices (hqc_autotune_decrypt: 7 rounds in shuffled order,
 // four back-to-back graph launches per sample, every candidate's messages
 // identical) at each power-of-two batch from 2^8 to 2^20 items: shape
-// (1 = A, 2 = B), tile, and the grid in workgroups per compute unit.  A batch uses the entry of its bucket (the power of two at
-// or above its size; 2^8 below, 2^20 above).
+// (1 = A, 2 = B), tile, and the grid in workgroups per compute unit.  A
+// batch uses the entry of its bucket (the power of two at or above its
+// size; 2^8 below, 2^20 above).
 struct BuiltinEntry {
   uint8_t shape, tile, wg_per_cu;
 };
@@ -407,11 +416,8 @@ int builtin_launch(int op, unsigned mask, uint64_t items, int *shape, uint32_t *
     b = b < kBuiltinLo ? kBuiltinLo : b > kBuiltinHi ? kBuiltinHi : b;
     const BuiltinEntry &e = kBuiltin[set][b - kBuiltinLo];
     if (shape_exists(op, mask, e.shape - 1)) {
-      int full = 0, cus = 0, dev = 0;
-      hipError_t he = hipGetDevice(&dev);
-      if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      if (he != hipSuccess) return hip_fail(he);
-      const int rc = default_grid(op, mask, &full, e.shape - 1);
+      int full = 0, cus = 0;
+      int rc = default_grid(op, mask, &full, e.shape - 1, &cus);
       if (rc) return rc;
       *shape = e.shape - 1;
       *tile = e.tile;
