@@ -74,7 +74,7 @@ int default_grid(int op, unsigned mask, int *out, int shape = 0, int *cus_out = 
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e);
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hqc::kernel_ptr(op, mask, shape), 64,
-                                                   hqc::lds_bytes_for(mask, shape));
+                                                   hqc::lds_bytes_for(op, mask, shape));
   if (e != hipSuccess) return hip_fail(e);
   if (per_cu < 1) per_cu = 1;
   *out = cus * per_cu;
@@ -134,7 +134,7 @@ int launch_graph(int op, unsigned mask, const hqc::KArgs &a, int grid, hipStream
     np.func = const_cast<void *>(hqc::kernel_ptr(op, mask, shape));
     np.gridDim = dim3((unsigned)grid);
     np.blockDim = dim3(64);
-    np.sharedMemBytes = (unsigned)hqc::lds_bytes_for(mask, shape);
+    np.sharedMemBytes = (unsigned)hqc::lds_bytes_for(op, mask, shape);
     np.kernelParams = params;
     hipGraphNode_t node;
     e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &np);
@@ -189,17 +189,17 @@ bool tuned_lookup(int pid, uint64_t count, int *tile, int *grid, int *shape) {
   return true;
 }
 
-// Relative time per item of the sets in the shape-A kernels at two
-// wavefronts per SIMD, as in the mixed-set kernels (HQC-1 = 64), from
-// single-set launches on MI355X (grid 2,048): decryption (and keyed
-// decryption) of 65,536 items (0.349 / 0.780 / 1.467 ms), decoding of
-// 262,144 words (0.451 / 0.721 / 1.413 ms).
+// Relative time per item of the sets in the shape-A kernels, as in the
+// mixed-set kernels (HQC-1 = 64), from single-set launches on MI355X:
+// decryption (and keyed decryption) of 65,536 items at two wavefronts per
+// SIMD (0.349 / 0.780 / 1.467 ms), decoding of 262,144 words in the decoding
+// layout (0.387 / 0.646 / 1.220 ms).
 uint32_t set_cost(int op, int pid) {
   const bool dec = op == hqc::OP_DECODE;
   switch (pid) {
     case 1: return 64;
-    case 3: return dec ? 102 : 143;
-    case 5: return dec ? 201 : 269;
+    case 3: return dec ? 107 : 143;
+    case 5: return dec ? 202 : 269;
     default: return 64;
   }
 }

@@ -27,10 +27,12 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // Kernel shapes of the decryption kernels (SH, a tuning knob; results never
 // depend on it): shape 0 for every set, and shape 1 for HQC-1 and HQC-3,
 // built for three wavefronts per SIMD instead of two (HQC-3 with the compact
-// LDS layout to fit them).  Key generation and encryption use shape 0's
-// sizes.
+// LDS layout to fit them).  SH 2 is the layout of the decoding kernels'
+// shape 0: decoding needs no doubled u, so their LDS holds the received
+// words and the symbol table only, and three wavefronts per SIMD fit for
+// every set.  Key generation and encryption use shape 0's sizes.
 template <int ID, int SH = 0> struct Geo {
-  static_assert(SH == 0 || (SH == 1 && ID != 5), "shape 1 exists for HQC-1 and HQC-3");
+  static_assert(SH == 0 || SH == 2 || (SH == 1 && ID != 5), "shape 1 exists for HQC-1 and HQC-3");
   using S = Set<ID>;
   static constexpr int n = S::n, n1 = S::n1, n2 = S::n2, k = S::k, w = S::w;
   static constexpr int MULT = n2 / 128;
@@ -53,14 +55,16 @@ template <int ID, int SH = 0> struct Geo {
   // fits in 20 KiB of LDS (eight wavefronts per CU; HQC-3 shape 1: 11 KiB)
   static constexpr bool COMPACT = ID == 5 || (ID == 3 && SH == 1);
   static constexpr int TROWS = COMPACT ? 32 : 64;    // items per (sub-)tile
-  static constexpr int RB_OFF = COMPACT ? 0 : U2;    // dword offset of the received word
+  static constexpr bool DECODE_ONLY = SH == 2;       // no doubled u in LDS
+  static constexpr int RB_OFF = (COMPACT || DECODE_ONLY) ? 0 : U2;  // dword offset of the received word
   // RM blocks are decoded 32 per pass, one per lane pair (matrix cores).
   // HQC-1 keeps the received words of RMG = 2 items and decodes their
   // 2 x 46 = 92 blocks in 3 passes instead of 2 x 2
   static constexpr int RMG = ID == 1 ? 2 : 1;
-  static constexpr int WAVES = SH == 1 ? 3 : 2;      // wavefronts per SIMD the kernel is built for
+  static constexpr int WAVES = SH == 0 ? 2 : 3;      // wavefronts per SIMD the kernel is built for
   static constexpr int A_BYTES =
-      (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
+      DECODE_ONLY ? (4 * RMG * RB + 15) / 16 * 16
+                  : (4 * (COMPACT ? cmax(U2, RB) : U2 + RMG * RB) + 15) / 16 * 16;
   static constexpr int LDS_BYTES = A_BYTES + TROWS * SSTR;
   // debug dump of one item (byte offsets; the record is a whole number of dwords)
   static constexpr int DBG_SYM = 4 * W32, DBG_S = DBG_SYM + n1, DBG_LAM = DBG_S + TD,

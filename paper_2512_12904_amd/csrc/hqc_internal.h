@@ -57,7 +57,7 @@ bool set_info(int pid, SetInfo *out);
 // shape: the kernel shape (0, or 1 for single-set HQC-1 / HQC-3 kernels
 // other than the debug one); kernel_ptr returns NULL where it does not exist.
 const void *kernel_ptr(int op, unsigned mask, int shape);
-size_t lds_bytes_for(unsigned mask, int shape);
+size_t lds_bytes_for(int op, unsigned mask, int shape);
 bool shape_exists(int op, unsigned mask, int shape);
 hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t stream,
                   int shape);

@@ -1035,9 +1035,11 @@ __device__ __forceinline__ void run_tile(const SegDev &sg, uint32_t item0, int n
   }
 }
 
-// shape 1 exists for single-set HQC-1 and HQC-3 kernels
+// shape 1 exists for single-set HQC-1 and HQC-3 kernels; SH 2 is the
+// decoding kernels' shape 0 (no doubled u in LDS)
 constexpr int kernel_waves(unsigned mask, int sh) {
-  return sh == 1 ? (mask == 1u ? Geo<1, 1>::WAVES : Geo<3, 1>::WAVES) : 2;
+  return sh == 2 ? Geo<5, 2>::WAVES
+                 : sh == 1 ? (mask == 1u ? Geo<1, 1>::WAVES : Geo<3, 1>::WAVES) : 2;
 }
 
 // The tiles of segment s that this workgroup takes (units blockIdx.x,
@@ -1062,11 +1064,13 @@ __device__ __forceinline__ void run_segment(const KArgs &a, int s, uint32_t *lds
 template <int OP, unsigned MASK, int SH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kernel_waves(MASK, SH)))) void
 hqc_kernel(KArgs a) {
-  static_assert(SH == 0 || MASK == 1u || MASK == 2u, "shape 1: HQC-1 or HQC-3 alone");
+  static_assert(SH != 1 || MASK == 1u || MASK == 2u, "shape 1: HQC-1 or HQC-3 alone");
+  static_assert(SH != 2 || OP == OP_DECODE, "the decoding layout keeps no doubled u");
   extern __shared__ uint32_t lds[];
   const GfTab exp4 = gf_exp_tab();
   const GfTab log4 = gf_log_tab();
-  constexpr int SH1 = MASK == 1u ? SH : 0, SH3 = MASK == 2u ? SH : 0;
+  constexpr int SH1 = (MASK == 1u || SH == 2) ? SH : 0, SH3 = (MASK == 2u || SH == 2) ? SH : 0;
+  constexpr int SH5 = SH == 2 ? 2 : 0;
   // the segment of each parameter set (each set appears at most once); the
   // sets run one after the other in straight-line code, so that no set's
   // loop-invariant registers stay live through another set's loop
@@ -1079,7 +1083,7 @@ hqc_kernel(KArgs a) {
   }
   if ((MASK & 1u) && s1 >= 0) run_segment<1, OP, SH1>(a, s1, lds, exp4, log4);
   if ((MASK & 2u) && s3 >= 0) run_segment<3, OP, SH3>(a, s3, lds, exp4, log4);
-  if ((MASK & 4u) && s5 >= 0) run_segment<5, OP, 0>(a, s5, lds, exp4, log4);
+  if ((MASK & 4u) && s5 >= 0) run_segment<5, OP, SH5>(a, s5, lds, exp4, log4);
 }
 
 template <int OP>
@@ -1091,14 +1095,16 @@ const void *kernel_for_mask(unsigned mask, int shape) {
     else if (mask == 2u) return (const void *)&hqc_kernel<OP, 2, 1>;
     return nullptr;
   }
+  // shape 0: decoding in its own layout (SH 2)
+  constexpr int S0 = OP == OP_DECODE ? 2 : 0;
   switch (mask) {
-    case 1: return (const void *)&hqc_kernel<OP, 1, 0>;
-    case 2: return (const void *)&hqc_kernel<OP, 2, 0>;
-    case 4: return (const void *)&hqc_kernel<OP, 4, 0>;
+    case 1: return (const void *)&hqc_kernel<OP, 1, S0>;
+    case 2: return (const void *)&hqc_kernel<OP, 2, S0>;
+    case 4: return (const void *)&hqc_kernel<OP, 4, S0>;
     default:
       // debug launches carry one parameter set: no mixed-set debug kernel
       if constexpr (OP == OP_DEBUG) return nullptr;
-      else return (const void *)&hqc_kernel<OP, 7, 0>;
+      else return (const void *)&hqc_kernel<OP, 7, S0>;
   }
 }
 
@@ -1142,17 +1148,17 @@ const void *kernel_ptr(int op, unsigned mask, int shape) {
   }
 }
 
-size_t lds_bytes_for(unsigned mask, int shape) {
+size_t lds_bytes_for(int op, unsigned mask, int shape) {
   if (shape == 1) {
     if (mask == 1u) return Geo<1, 1>::LDS_BYTES;
     if (mask == 2u) return Geo<3, 1>::LDS_BYTES;
     return 0;
   }
+  const bool dec = op == OP_DECODE;
   size_t b = 0;
-  SetInfo si;
-  if (mask & 1u) { set_info(1, &si); b = si.lds_bytes > b ? si.lds_bytes : b; }
-  if (mask & 2u) { set_info(3, &si); b = si.lds_bytes > b ? si.lds_bytes : b; }
-  if (mask & 4u) { set_info(5, &si); b = si.lds_bytes > b ? si.lds_bytes : b; }
+  if (mask & 1u) b = cmax((int)b, dec ? Geo<1, 2>::LDS_BYTES : Geo<1, 0>::LDS_BYTES);
+  if (mask & 2u) b = cmax((int)b, dec ? Geo<3, 2>::LDS_BYTES : Geo<3, 0>::LDS_BYTES);
+  if (mask & 4u) b = cmax((int)b, dec ? Geo<5, 2>::LDS_BYTES : Geo<5, 0>::LDS_BYTES);
   return b;
 }
 
@@ -1165,7 +1171,7 @@ hipError_t launch(int op, unsigned mask, const KArgs &a, int grid, hipStream_t s
   if (!fn) return hipErrorInvalidDeviceFunction;
   KArgs copy = a;
   void *args[] = {&copy};
-  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), args, lds_bytes_for(mask, shape),
+  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), args, lds_bytes_for(op, mask, shape),
                          stream);
 }
 

@@ -1,9 +1,10 @@
 // Host-side check of the GPU kernels' index arithmetic (built host-only by
 // tests/test_bounds_model.py; no GPU needed).  It evaluates the index
 // functions the kernels themselves call (Layout<G> in hqc_device.h) for every
-// geometry the library instantiates -- HQC-1/3/5 in shape 0, HQC-1/3 in
-// shape 1 -- over every lane, every shift of the product windows, every
-// tile size and every RM pass of the pass schedule, and checks each LDS
+// geometry the library instantiates -- HQC-1/3/5 in shape 0 and in the
+// decoding layout, HQC-1/3 in shape 1 -- over every lane, every shift of the
+// product windows, every tile size and every RM pass of the pass schedule,
+// and checks each LDS
 // offset against the layout's region and the dynamic LDS size, and each row
 // offset against the row sizes of the device buffers.  Prints one line per
 // geometry and exits non-zero on the first violation.
@@ -33,15 +34,18 @@ template <int ID, int SH> void check_decrypt(const char *name) {
   CHECK(name, G::LDS_BYTES % 4 == 0 && G::A_BYTES % 16 == 0, "alignment", G::LDS_BYTES, G::A_BYTES);
   CHECK(name, G::LDS_BYTES * 4 * G::WAVES <= 160 * 1024, "LDS of the resident wavefronts",
         G::LDS_BYTES * 4 * G::WAVES, 160 * 1024);
-  // S0: the doubled copy (written for D < U2) lies in the first region
-  CHECK(name, G::U2 <= a_dw, "doubled copy inside the received-word region", G::U2, a_dw);
-  CHECK(name, G::COMPACT || L::rb(0) >= G::U2, "rows after the doubled copy", L::rb(0), G::U2);
-  // S1: every product window dword, every lane, every shift in [1, n]
-  for (int lane = 0; lane < 64; ++lane)
-    for (uint32_t sh = 1; sh <= (uint32_t)G::n; ++sh) {
-      const int lo = L::window(lane, sh, 0), hi = L::window(lane, sh, G::R);
-      CHECK(name, lo >= 0 && hi < G::U2, "product window inside the doubled copy", hi, G::U2);
-    }
+  // S0: the doubled copy (written for D < U2) lies in the first region --
+  // except in the decoding layout, which has none
+  if constexpr (!G::DECODE_ONLY) {
+    CHECK(name, G::U2 <= a_dw, "doubled copy inside the received-word region", G::U2, a_dw);
+    CHECK(name, G::COMPACT || L::rb(0) >= G::U2, "rows after the doubled copy", L::rb(0), G::U2);
+    // S1: every product window dword, every lane, every shift in [1, n]
+    for (int lane = 0; lane < 64; ++lane)
+      for (uint32_t sh = 1; sh <= (uint32_t)G::n; ++sh) {
+        const int lo = L::window(lane, sh, 0), hi = L::window(lane, sh, G::R);
+        CHECK(name, lo >= 0 && hi < G::U2, "product window inside the doubled copy", hi, G::U2);
+      }
+  }
   // S2: received-word rows of every slot
   for (int q = 0; q < G::RMG; ++q) {
     for (int d = 0; d < G::W32; ++d) {
@@ -49,11 +53,12 @@ template <int ID, int SH> void check_decrypt(const char *name) {
       CHECK(name, o >= L::rb(q) && o < L::rb(q) + G::RB, "row inside its slot", o, L::rb(q) + G::RB);
       CHECK(name, o < a_dw, "row inside the region", o, a_dw);
     }
-    for (int lane = 0; lane < 64; ++lane)
-      for (int j = 0; j < G::R; ++j) {
-        const int d = L::out(lane, j);
-        if (d < G::W32) CHECK(name, L::rb(q) + L::row(d) < a_dw, "product row", d, a_dw);
-      }
+    if constexpr (!G::DECODE_ONLY)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int j = 0; j < G::R; ++j) {
+          const int d = L::out(lane, j);
+          if (d < G::W32) CHECK(name, L::rb(q) + L::row(d) < a_dw, "product row", d, a_dw);
+        }
   }
   // S3-S5: the RM pass schedule for every tile size, and the symbol stores
   for (int nt = 1; nt <= G::TROWS; ++nt) {
@@ -184,6 +189,10 @@ int main() {
   std::printf("decrypt HQC-3 shape B ok\n");
   check_decrypt<5, 0>("decrypt HQC-5");
   std::printf("decrypt HQC-5 ok\n");
+  check_decrypt<1, 2>("decode HQC-1");
+  check_decrypt<3, 2>("decode HQC-3");
+  check_decrypt<5, 2>("decode HQC-5");
+  std::printf("decoding layouts ok\n");
   check_encrypt<1>("encrypt HQC-1");
   check_encrypt<3>("encrypt HQC-3");
   check_encrypt<5>("encrypt HQC-5");

@@ -25,4 +25,4 @@ def test_kernel_index_bounds(tmp_path):
                           stderr=subprocess.DEVNULL)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count(" ok") == 7, r.stdout
+    assert r.stdout.count(" ok") == 8, r.stdout
