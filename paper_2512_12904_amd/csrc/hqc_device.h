@@ -308,15 +308,47 @@ __device__ __forceinline__ void window_shifts(const uint32_t (&idx)[NREG], uint3
   for (int c = 0; c < NREG; ++c) sh[c] = (uint32_t)G::n - idx[c] % (uint32_t)G::n;
 }
 
+// NP pairs of shifts, from packed dwords p .. p + NP - 1 of pk (two 16-bit
+// shifts a dword): their 2 NP windows are loaded together, then each pair is
+// combined with a three-way XOR
+template <int ID, int NP>
+__device__ __forceinline__ void product_pairs(const uint32_t *u2, uint32_t pk, int p, int lane,
+                                              uint32_t (&acc)[Geo<ID>::R]) {
+  using G = Geo<ID>;
+  using L = Layout<G>;
+  uint32_t win[2 * NP][G::R + 1], shs[2 * NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const uint32_t w = rdlane(pk, p + q);
+    shs[2 * q] = w & 0xFFFFu;
+    shs[2 * q + 1] = w >> 16;
+  }
+#pragma unroll
+  for (int q = 0; q < 2 * NP; ++q)
+#pragma unroll
+    for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
+#pragma unroll
+  for (int q = 0; q < 2 * NP; q += 2)
+#pragma unroll
+    for (int j = 0; j < G::R; ++j)
+      acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
+                    __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
+}
+
 // acc[j] ^= bits [32 (lane R + j) + sh_k, +32) of U2 for the first NIDX
 // shifts: lane l's R output dwords of (sum_k X^{index_k}) * a, restricted to
-// the dwords below 64 R.  The windows of U consecutive indices are loaded
-// together, then combined two at a time with a three-way XOR.
+// the dwords below 64 R.  The shifts of a register's cnt indices are first
+// packed two to a dword (lane l < cnt / 2 holds those of lanes l and
+// l + ceil(cnt / 2); every shift is at most n < 2^16), so one lane read
+// serves two indices; the windows of U indices are loaded together, then
+// combined two at a time with a three-way XOR.  The XOR sum does not depend
+// on the order the indices are taken in.
 template <int ID, int NIDX>
 __device__ __forceinline__ void product_acc(const uint32_t *u2,
                                             const uint32_t (&shreg)[(NIDX + 63) / 64],
                                             uint32_t (&acc)[Geo<ID>::R]) {
   using G = Geo<ID>;
+  static_assert(G::n < 65536, "shifts are packed as 16-bit halves");
   constexpr int NREG = (NIDX + 63) / 64;
   using L = Layout<G>;
   const int lane = lane_id();
@@ -324,25 +356,25 @@ __device__ __forceinline__ void product_acc(const uint32_t *u2,
 #pragma unroll
   for (int c = 0; c < NREG; ++c) {
     const int cnt = (NIDX - 64 * c) < 64 ? (NIDX - 64 * c) : 64;
-    int kk = 0;
-    for (; kk + U <= cnt; kk += U) {
-      uint32_t win[U][G::R + 1], shs[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        shs[q] = rdlane(shreg[c], kk + q);
-#pragma unroll
-        for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
-      }
-#pragma unroll
-      for (int q = 0; q < U; q += 2)
-#pragma unroll
-        for (int j = 0; j < G::R; ++j)
-          acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
-                        __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
+    const int half = (cnt + 1) / 2;
+    uint32_t hi;
+    if (half == 32) {
+      hi = halves(shreg[c]).hi;
+    } else {
+      // lane (l + half) mod 64's shift; lanes past the register's indices
+      // read values that are never used
+      hi = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + half) << 2, (int)shreg[c]);
     }
-    for (; kk < cnt; ++kk) {
+    const uint32_t pk = shreg[c] | hi << 16;
+    const int np = cnt / 2;
+    int p = 0;
+    for (; p + U / 2 <= np; p += U / 2) product_pairs<ID, U / 2>(u2, pk, p, lane, acc);
+    if constexpr (U / 2 > 1)
+      for (; p < np; ++p) product_pairs<ID, 1>(u2, pk, p, lane, acc);
+    if (cnt & 1) {
+      // the odd index: lane np's low half
       uint32_t win[G::R + 1];
-      const uint32_t sh = rdlane(shreg[c], kk);
+      const uint32_t sh = rdlane(pk, np) & 0xFFFFu;
 #pragma unroll
       for (int j = 0; j <= G::R; ++j) win[j] = u2[L::window(lane, sh, j)];
 #pragma unroll
