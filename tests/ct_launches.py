@@ -1,16 +1,24 @@
-"""Decryption launches of three input classes in a seeded random order, for
-the constant-time test (tests/test_gpu_timing.py runs this script under
+"""Calls of three input classes in a seeded random order, for the
+constant-time tests (tests/test_gpu_timing.py runs this script under
 rocprofv3's counter collection and reads the per-dispatch counters).
 
-usage: python ct_launches.py PID REPS ORDER_JSON
+usage: python ct_launches.py decrypt|decaps PID REPS ORDER_JSON
 
-Classes (16,384 items each, the library's default launch for that size):
+decrypt -- one decryption launch per call (16,384 items, the library's
+default launch for that size), classes:
   zero:   one fixed key, u = 0, v = codewords of random messages (the decoder
           sees no error: every syndrome is zero, Lambda = 1);
   honest: one fixed key, honest ciphertexts (decryption recovers m);
   random: fresh random keys and uniformly random (u, v) (every word is past
           the decoding radius, so Berlekamp-Massey runs at full degree).
-Writes the class name of every decryption launch, in launch order, to
+decaps -- one KEM decapsulation per call (16,384 items, 256 keys), classes:
+  honest:   honest encapsulations (the re-encryption check passes);
+  tampered: the same with one bit of v flipped (rejected by the check);
+  random:   uniformly random (u, v) (rejected, past the decoding radius).
+Each call first copies its class's inputs into one set of buffers that
+every class shares, so that the classes differ in data only, not in the
+addresses the kernels read (the copies are not library kernels and are not
+counted).  Writes the class name of every timed call, in call order, to
 ORDER_JSON and prints 'launches done' last."""
 import json
 import os
@@ -49,25 +57,78 @@ def classes(pid, dev="cuda"):
     return c, d["m"][idx], p
 
 
-def main():
-    pid, reps, order_path = int(sys.argv[1]), int(sys.argv[2]), sys.argv[3]
+def decaps_calls(pid, dev="cuda"):
+    """the three decapsulation classes as calls; checks that each class is
+    what it claims"""
+    import torch
+    from paper_2512_12904_amd import hqc, synth
+    from tests import datasets
+
+    def T(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(dev)
+
+    p = datasets.sizes(pid)
+    n, nkeys = COUNT, 256
+    d = datasets.pke(pid, nkeys, 0xC80 + pid)
+    idx = np.arange(n) % nkeys
+    h, s, y = T(d["h"][idx], np.int64), T(d["s"][idx], np.int64), T(d["y_keys"][idx], np.int32)
+    m = T(synth.words(0xC81 + pid, (n, p["k"] // 8)).view(np.uint8), np.uint8)
+    sigma = T(synth.words(0xC82 + pid, (n, p["k"] // 8)).view(np.uint8), np.uint8)
+    u, v, key = hqc.kem_encaps_batch(pid, h, s, m)
+    vt = v.clone()
+    vt[:, 0] ^= 1
+    c = {"honest": (u, v), "tampered": (u, vt),
+         "random": (T(synth.words(0xC83 + pid, (n, p["nwords"])), np.int64),
+                    T(synth.words(0xC84 + pid, (n, p["vwords"])), np.int64))}
+    ws = torch.empty(hqc.kem_workspace_bytes(pid, n), dtype=torch.uint8, device=dev)
+    out = torch.empty((n, hqc.KEM_KEY_BYTES), dtype=torch.uint8, device=dev)
+    buf = tuple(torch.empty_like(a) for a in c["honest"])
+
+    def run(name):
+        # every class is decapsulated from the same buffers (only their
+        # contents differ, not the addresses the kernels read)
+        for b, a in zip(buf, c[name]):
+            b.copy_(a)
+        return hqc.kem_decaps_batch(pid, h, s, y, sigma, *buf, key_out=out, workspace=ws)
+
+    ok = torch.equal(run("honest"), key) and not (run("tampered") == key).all(dim=1).any()
+    torch.cuda.synchronize()
+    return list(c), run, bool(ok)
+
+
+def decrypt_calls(pid):
     import torch
     from paper_2512_12904_amd import hqc
-    print("classes pid=%d" % pid, flush=True)
     c, m_honest, p = classes(pid)
-    names = list(c)
     out = torch.empty((COUNT, p["k"]), dtype=torch.uint8, device="cuda")
+    buf = tuple(torch.empty_like(a) for a in c["honest"])
+
+    def run(name):
+        # every class is decrypted from the same buffers (only their
+        # contents differ, not the addresses the kernel reads)
+        for b, a in zip(buf, c[name]):
+            b.copy_(a)
+        return hqc.decrypt_batch(pid, *buf, out=out)
+
     # the honest class decrypts to its messages (the timing is of real
     # decryptions)
-    hqc.decrypt_batch(pid, *c["honest"], out=out)
+    run("honest")
     torch.cuda.synchronize()
-    if not np.array_equal(out.cpu().numpy(), m_honest):
-        print("honest class not recovered", flush=True)
+    return list(c), run, bool(np.array_equal(out.cpu().numpy(), m_honest))
+
+
+def main():
+    mode, pid, reps, order_path = sys.argv[1], int(sys.argv[2]), int(sys.argv[3]), sys.argv[4]
+    import torch
+    print("classes %s pid=%d" % (mode, pid), flush=True)
+    names, run, ok = {"decrypt": decrypt_calls, "decaps": decaps_calls}[mode](pid)
+    if not ok:
+        print("a class is not what it claims", flush=True)
         sys.exit(3)
     order = np.random.default_rng(pid).permutation(np.repeat(np.arange(len(names)), reps))
     seq = []
     for i in order:
-        hqc.decrypt_batch(pid, *c[names[i]], out=out)
+        run(names[i])
         seq.append(names[i])
     torch.cuda.synchronize()
     with open(order_path, "w") as f:
