@@ -775,6 +775,9 @@ def main():
             # this kernel source, beside the op-model fraction
             r["valu_busy_counters"] = cc["valu_busy"]
             r["valu_insts_per_decrypt"] = cc["valu_insts_per_item"]
+            # the second pipe the product loads: LDS cycles spent on
+            # indexed accesses per CU cycle
+            r["lds_active_counters"] = cc.get("lds_active")
         t = tuned.get(pid)
         if t is None and not args.no_autotune and GRID == 0 and TILE == 0 and SHAPE == 0:
             # after timing: the autotuner's search for this set and size,
@@ -841,6 +844,7 @@ def main():
                      "frac_transform_on_vector": op_model_vector_transform(pid0) * args.count
                      / (main_r["ms_mean"] / 1e3) / PEAK_INT_OPS,
                      "valu_busy_counters": main_r.get("valu_busy_counters"),
+                     "lds_active_counters": main_r.get("lds_active_counters"),
                      "matrix": {"ops_per_decrypt": matrix_ops(pid0),
                                 "achieved": matrix_ops(pid0) * args.count
                                 / (main_r["ms_mean"] / 1e3) / 1e12,
@@ -857,6 +861,7 @@ def main():
         cc = committed_counters("decode_mixed")
         if cc:
             line["decode_stress"]["valu_busy_counters"] = cc["valu_busy"]
+            line["decode_stress"]["lds_active_counters"] = cc.get("lds_active")
             line["decode_stress"]["valu_insts_per_word"] = cc["valu_insts_per_item"]
         if not line["decode_stress"]["all_messages_recovered"]:
             print("decoder stress: messages differ from the encoded ones", file=sys.stderr)
