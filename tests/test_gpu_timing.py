@@ -1,38 +1,37 @@
 """Timing checks of decryption and decapsulation against their input data,
-in the style of dudect (Reparaz, Balasch, Verbauwhede, "Dude, is my code
-constant time?", 2017): calls of input classes made interleaved in a seeded
-random order, measured per call.
+after dudect (Reparaz, Balasch, Verbauwhede, "Dude, is my code constant
+time?", 2017): calls of input classes made interleaved in a seeded random
+order, measured per call, compared between classes.
 
 Both run tests/ct_launches.py under rocprofv3's counter collection, which
 copies each call's inputs into one set of buffers shared by all classes (so
-that only the data differ, not the addresses read).  Every dispatch of a
-kernel must execute the same instructions (VALU, SALU, LDS) with the same
-LDS bank conflicts in every class: the deterministic form of the check.
-Durations are taken in shader-clock cycles (SQ_BUSY_CYCLES) and in wall
-time.  Cycles, because the chip runs its clock faster on data that switches
-fewer bits: all-zero data give 2-4 % shorter decryption launches at equal
-cycle counts, which a t statistic over wall time flags at any launch size
-given enough launches, though no instruction differs.
+that only the data differ, not the addresses read).  The deterministic
+check: every dispatch of a kernel executes the same instructions (VALU,
+SALU, LDS) with the same LDS bank conflicts in every class -- a branch or
+loop that depended on the data would change these counts.  The statistical
+check: durations in shader-clock cycles (SQ_BUSY_CYCLES) and in wall time,
+with the mean of every class within a bound of the reference class's.
+
+No bound is placed on Welch's t (it is printed).  Wall time differs between
+classes that run the same instructions because the chip clocks higher on
+data that switch fewer bits: all-zero data give 4-5 % shorter decryption
+launches at equal cycle counts, honest data up to 1.5 % (wall-time |t| up
+to 17 with 40 calls a class).  Cycles remove most of that, but not all:
+over repeated runs the honest and random decryption classes differed by up
+to 0.2 % in mean cycles (|t| from 0.1 to 7.4, on different boxes), with
+identical instruction counts, and the decapsulation key kernel (one
+wavefront per CU, mostly waiting on memory) by up to 0.3 %.
 
 Decryption: classes zero (u = 0, v = codewords: no error at all), honest
 (honest ciphertexts under one key) and random (random keys, uniform u and
-v: every word past the decoding radius).  dudect's criterion, Welch's
-|t| < 4.5, on the cycles of honest against random; the mean cycles of
-every class within 1 % of random and the wall times within 2 % (honest) /
-5 % (zero).  The all-zero class is held to the bounds only: in cycles too
-it differs by about 0.1 % (|t| up to about 3 with 40 calls a class) --
-plausibly the launch's waits on memory, whose latency is fixed in
-nanoseconds, counting more cycles at the higher clock.
+v: every word past the decoding radius).  Mean cycles within 0.5 % of
+random, wall times within 2 % (honest) / 5 % (zero).
 
 Decapsulation: classes honest, tampered (one bit of v flipped: rejected by
 the re-encryption check) and random (rejected, past the decoding radius);
 each call is four launches (decryption, SHAKE256 draws, sampling with the
-re-encryption check, key).  Per call, the cycles of its kernels are summed:
-within 1 % of the honest class's, wall times within 2 % (tampered) / 5 %
-(random).  No t criterion here: the key kernel runs one wavefront per CU
-and waits on memory most of its time, and its cycles differ between the
-classes by 0.1-0.3 % with the same instructions and addresses (|t| up to
-15 for HQC-3)."""
+re-encryption check, key), their cycles summed: within 0.5 % of the honest
+class's, wall times within 2 % (tampered) / 5 % (random)."""
 import csv
 import glob
 import json
@@ -47,16 +46,14 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-# dudect's threshold on Welch's t between two classes
-T_BOUND = 4.5
 # bounds on |mean(class) / mean(reference class) - 1| of wall times
 # (measured: up to about 1 % honest and 2-4 % all-zero, at equal cycles)
 HONEST_BOUND = 0.02
 ZERO_BOUND = 0.05
 # bound on the relative difference of mean cycles (measured: at most about
-# 0.3 %; skipping a pass of the decoder would change far more, and the
-# instruction counts besides)
-CYCLE_BOUND = 0.01
+# 0.2 % for decryption, 0.1 % for a whole decapsulation; skipping a pass of
+# the decoder would change far more, and the instruction counts besides)
+CYCLE_BOUND = 0.005
 # counters that must be equal in every dispatch, and the cycle counter
 SAME = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT"]
 CYCLES = "SQ_BUSY_CYCLES"
@@ -129,10 +126,10 @@ def profile_calls(mode, pid, tmp):
     return order, calls
 
 
-def check_classes(mode, pid, tmp, names, ref, t_classes, cycle_bounds, wall_bounds):
-    """the same instructions per kernel in every call; dudect's criterion on
-    the cycles per call of t_classes against the reference class; bounds on
-    the relative difference of the mean cycles and wall times"""
+def check_classes(mode, pid, tmp, names, ref, cycle_bounds, wall_bounds):
+    """the same instructions per kernel in every call; bounds on the
+    relative difference of the mean cycles and wall times per call against
+    the reference class"""
     order, calls = profile_calls(mode, pid, tmp)
     assert sorted(set(order)) == sorted(names) and len(order) == len(names) * REPS
     for j in range(len(calls[0])):
@@ -149,8 +146,6 @@ def check_classes(mode, pid, tmp, names, ref, t_classes, cycle_bounds, wall_boun
         print("%s pid %d %-8s cycles %.0f (t vs %s %.2f, %+.3f %%)  wall %.4f ms (t vs %s %.2f, %+.2f %%)" % (
             mode, pid, n, cyc[n].mean(), ref, t[n], 100 * rc[n], wall[n].mean() / 1e6, ref,
             welch_t(wall[n], wall[ref]), 100 * rw[n]), flush=True)
-    for n in t_classes:
-        assert abs(t[n]) < T_BOUND, (n, t[n])
     for n, bound in cycle_bounds.items():
         assert abs(rc[n]) < bound, rc
     for n, bound in wall_bounds.items():
@@ -163,7 +158,7 @@ def test_decrypt_time_independent_of_data(pid, tmp_path):
     if torch.cuda.device_count() == 0:
         pytest.skip("no GPU")
     check_classes("decrypt", pid, str(tmp_path), ["zero", "honest", "random"], "random",
-                  t_classes=["honest"], cycle_bounds={"honest": CYCLE_BOUND, "zero": CYCLE_BOUND},
+                  cycle_bounds={"honest": CYCLE_BOUND, "zero": CYCLE_BOUND},
                   wall_bounds={"honest": HONEST_BOUND, "zero": ZERO_BOUND})
 
 
@@ -179,5 +174,5 @@ def test_decaps_time_independent_of_rejection(pid, tmp_path):
     if torch.cuda.device_count() == 0:
         pytest.skip("no GPU")
     check_classes("decaps", pid, str(tmp_path), ["honest", "tampered", "random"], "honest",
-                  t_classes=[], cycle_bounds={"tampered": CYCLE_BOUND, "random": CYCLE_BOUND},
+                  cycle_bounds={"tampered": CYCLE_BOUND, "random": CYCLE_BOUND},
                   wall_bounds={"tampered": HONEST_BOUND, "random": ZERO_BOUND})
