@@ -24,8 +24,8 @@ wavefront per CU, mostly waiting on memory) by up to 0.3 %.
 
 Decryption: classes zero (u = 0, v = codewords: no error at all), honest
 (honest ciphertexts under one key) and random (random keys, uniform u and
-v: every word past the decoding radius).  Mean cycles within 0.5 % of
-random, wall times within 2 % (honest) / 5 % (zero).
+v: every word past the decoding radius).  Mean cycles within 0.5 %
+(honest) / 1 % (zero) of random, wall times within 2 % / 5 %.
 
 Decapsulation: classes honest, tampered (one bit of v flipped: rejected by
 the re-encryption check) and random (rejected, past the decoding radius);
@@ -54,6 +54,9 @@ ZERO_BOUND = 0.05
 # 0.2 % for decryption, 0.1 % for a whole decapsulation; skipping a pass of
 # the decoder would change far more, and the instruction counts besides)
 CYCLE_BOUND = 0.005
+# the all-zero class, the extreme of low switching activity: measured up to
+# 0.23 % in cycles
+ZERO_CYCLE_BOUND = 0.01
 # counters that must be equal in every dispatch, and the cycle counter
 SAME = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT"]
 CYCLES = "SQ_BUSY_CYCLES"
@@ -158,7 +161,7 @@ def test_decrypt_time_independent_of_data(pid, tmp_path):
     if torch.cuda.device_count() == 0:
         pytest.skip("no GPU")
     check_classes("decrypt", pid, str(tmp_path), ["zero", "honest", "random"], "random",
-                  cycle_bounds={"honest": CYCLE_BOUND, "zero": CYCLE_BOUND},
+                  cycle_bounds={"honest": CYCLE_BOUND, "zero": ZERO_CYCLE_BOUND},
                   wall_bounds={"honest": HONEST_BOUND, "zero": ZERO_BOUND})
 
 
