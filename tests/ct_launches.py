@@ -57,6 +57,49 @@ def classes(pid, dev="cuda"):
     return c, d["m"][idx], p
 
 
+def library_kernel(name):
+    return "hqc_" in name or "kem_" in name
+
+
+def parse_profile(cc_path, kt_path, n_calls, per_call=None):
+    """The library dispatches of the last n_calls calls from rocprofv3's
+    counter-collection and kernel-trace CSV files: per call a list of
+    (kernel name, {counter: value summed over its rows}, duration in ns).
+    Every call makes the same sequence of per_call library dispatches; when
+    per_call is None it is the period of the kernel-name sequence at the
+    end of the run.  Earlier dispatches (class checks, other kernels) are
+    left out."""
+    import csv
+    counters, names = {}, {}
+    with open(cc_path) as f:
+        for row in csv.DictReader(f):
+            if library_kernel(row["Kernel_Name"]):
+                i = int(row["Dispatch_Id"])
+                d = counters.setdefault(i, {})
+                d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+                names[i] = row["Kernel_Name"]
+    ns = {}
+    with open(kt_path) as f:
+        for row in csv.DictReader(f):
+            if library_kernel(row["Kernel_Name"]):
+                ns[int(row["Dispatch_Id"])] = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+    ids = sorted(counters)
+    k = per_call
+    if k is None:
+        k = next((kk for kk in range(1, 9) if len(ids) >= 4 * kk and
+                  all(names[ids[-j - 1]] == names[ids[-j - 1 - kk]] for j in range(3 * kk))), None)
+        if k is None:
+            raise ValueError("no repeating dispatch sequence")
+    ids = ids[-k * n_calls:]
+    if len(ids) != k * n_calls or any(i not in ns for i in ids):
+        raise ValueError("%d library dispatches for %d calls of %d" % (len(ids), n_calls, k))
+    calls = [[(names[i], counters[i], ns[i]) for i in ids[c * k:(c + 1) * k]] for c in range(n_calls)]
+    for c in calls:
+        if [n for n, _, _ in c] != [n for n, _, _ in calls[0]]:
+            raise ValueError("calls launch different kernels")
+    return calls
+
+
 def decaps_calls(pid, dev="cuda"):
     """the three decapsulation classes as calls; checks that each class is
     what it claims"""

@@ -32,7 +32,6 @@ the re-encryption check) and random (rejected, past the decoding radius);
 each call is four launches (decryption, SHAKE256 draws, sampling with the
 re-encryption check, key), their cycles summed: within 0.5 % of the honest
 class's, wall times within 2 % (tampered) / 5 % (random)."""
-import csv
 import glob
 import json
 import os
@@ -42,6 +41,8 @@ import sys
 
 import numpy as np
 import pytest
+
+from tests.ct_launches import parse_profile
 
 
 pytestmark = pytest.mark.gpu
@@ -75,10 +76,6 @@ def cropped(x, frac=0.95):
     return x[:max(2, int(frac * len(x)))]
 
 
-def library_kernel(name):
-    return "hqc_" in name or "kem_" in name
-
-
 def profile_calls(mode, pid, tmp):
     """run tests/ct_launches.py under rocprofv3; returns the class of every
     timed call and, per call, its library dispatches as (kernel name,
@@ -102,30 +99,7 @@ def profile_calls(mode, pid, tmp):
     cc = glob.glob(os.path.join(tmp, "prof", "**", "c_counter_collection.csv"), recursive=True)
     kt = glob.glob(os.path.join(tmp, "prof", "**", "c_kernel_trace.csv"), recursive=True)
     assert len(cc) == 1 and len(kt) == 1, (cc, kt, tail)
-    counters, names = {}, {}
-    for row in csv.DictReader(open(cc[0])):
-        if library_kernel(row["Kernel_Name"]):
-            i = int(row["Dispatch_Id"])
-            d = counters.setdefault(i, {})
-            d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
-            names[i] = row["Kernel_Name"]
-    ns = {}
-    for row in csv.DictReader(open(kt[0])):
-        if library_kernel(row["Kernel_Name"]):
-            ns[int(row["Dispatch_Id"])] = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
-    # every call makes the same sequence of k library dispatches; the timed
-    # calls are the last len(order) of them (earlier ones check the classes)
-    ids = sorted(counters)
-    k = {"decrypt": 1, "decaps": None}[mode]
-    if k is None:
-        # the period of the kernel-name sequence over the timed calls
-        k = next(kk for kk in range(1, 9)
-                 if all(names[ids[-j - 1]] == names[ids[-j - 1 - kk]] for j in range(3 * kk)))
-    ids = ids[-k * len(order):]
-    assert len(ids) == k * len(order) and all(i in ns for i in ids), (len(ids), k, len(order))
-    calls = [[(names[i], counters[i], ns[i]) for i in ids[c * k:(c + 1) * k]] for c in range(len(order))]
-    for c in calls:
-        assert [n for n, _, _ in c] == [n for n, _, _ in calls[0]], (c, calls[0])
+    calls = parse_profile(cc[0], kt[0], len(order), 1 if mode == "decrypt" else None)
     return order, calls
 
 
