@@ -383,61 +383,5 @@ __device__ __forceinline__ void product_acc(const uint32_t *u2,
   }
 }
 
-// product_acc with the windows of the next group of U indices loaded while
-// the current group is combined (two register sets of windows): the LDS
-// latency of a group overlaps the previous group's funnel shifts.
-template <int ID, int NIDX>
-__device__ __forceinline__ void product_acc_pipelined(const uint32_t *u2,
-                                                      const uint32_t (&shreg)[(NIDX + 63) / 64],
-                                                      uint32_t (&acc)[Geo<ID>::R]) {
-  using G = Geo<ID>;
-  constexpr int NREG = (NIDX + 63) / 64;
-  using L = Layout<G>;
-  const int lane = lane_id();
-  constexpr int U = G::R <= 10 ? 4 : 2;
-  auto load = [&](uint32_t (&win)[U][G::R + 1], uint32_t (&shs)[U], int c, int k0) {
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      shs[q] = rdlane(shreg[c], k0 + q);
-#pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
-    }
-  };
-  auto combine = [&](const uint32_t (&win)[U][G::R + 1], const uint32_t (&shs)[U]) {
-#pragma unroll
-    for (int q = 0; q < U; q += 2)
-#pragma unroll
-      for (int j = 0; j < G::R; ++j)
-        acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
-                      __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
-  };
-#pragma unroll
-  for (int c = 0; c < NREG; ++c) {
-    const int cnt = (NIDX - 64 * c) < 64 ? (NIDX - 64 * c) : 64;
-    uint32_t wa[U][G::R + 1], wb[U][G::R + 1], sa[U], sb[U];
-    int kk = 0;
-    if (cnt >= U) load(wa, sa, c, 0);
-    // invariant at the top: wa holds group kk when kk + U <= cnt
-    for (; kk + 2 * U <= cnt; kk += 2 * U) {
-      load(wb, sb, c, kk + U);
-      combine(wa, sa);
-      if (kk + 3 * U <= cnt) load(wa, sa, c, kk + 2 * U);
-      combine(wb, sb);
-    }
-    if (kk + U <= cnt) {
-      combine(wa, sa);
-      kk += U;
-    }
-    for (; kk < cnt; ++kk) {
-      uint32_t win[G::R + 1];
-      const uint32_t sh = rdlane(shreg[c], kk);
-#pragma unroll
-      for (int j = 0; j <= G::R; ++j) win[j] = u2[L::window(lane, sh, j)];
-#pragma unroll
-      for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
-    }
-  }
-}
-
 }  // namespace
 }  // namespace hqc

@@ -231,6 +231,80 @@ __device__ __forceinline__ void floyd3(uint32_t (&p)[3][(W + 63) / 64]) {
       p[v][c] = __builtin_amdgcn_inverse_ballot_w64(dup[v][c]) ? (uint32_t)(64 * c + lane) : p[v][c];
 }
 
+// product_acc with the windows of the next group of U indices loaded while
+// the current group is combined (two register sets of windows): the LDS
+// latency of a group overlaps the previous group's funnel shifts.  The
+// shifts are packed as in product_acc; slot 2p and 2p + 1 of a register are
+// the two halves of packed dword p (slot cnt - 1 of an odd count: the low
+// half alone), and a group of U slots starts at an even slot.
+template <int ID, int NIDX>
+__device__ __forceinline__ void product_acc_pipelined(const uint32_t *u2,
+                                                      const uint32_t (&shreg)[(NIDX + 63) / 64],
+                                                      uint32_t (&acc)[Geo<ID>::R]) {
+  using G = Geo<ID>;
+  static_assert(G::n < 65536, "shifts are packed as 16-bit halves");
+  constexpr int NREG = (NIDX + 63) / 64;
+  using L = Layout<G>;
+  const int lane = lane_id();
+  constexpr int U = G::R <= 10 ? 4 : 2;
+  static_assert(U % 2 == 0, "groups of whole pairs");
+  auto slot = [&](uint32_t pk, int k) {
+    const uint32_t w = rdlane(pk, k >> 1);
+    return (k & 1) ? w >> 16 : w & 0xFFFFu;
+  };
+  auto load = [&](uint32_t (&win)[U][G::R + 1], uint32_t (&shs)[U], uint32_t pk, int k0) {
+#pragma unroll
+    for (int q = 0; q < U; q += 2) {
+      const uint32_t w = rdlane(pk, (k0 + q) >> 1);
+      shs[q] = w & 0xFFFFu;
+      shs[q + 1] = w >> 16;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int j = 0; j <= G::R; ++j) win[q][j] = u2[L::window(lane, shs[q], j)];
+  };
+  auto combine = [&](const uint32_t (&win)[U][G::R + 1], const uint32_t (&shs)[U]) {
+#pragma unroll
+    for (int q = 0; q < U; q += 2)
+#pragma unroll
+      for (int j = 0; j < G::R; ++j)
+        acc[j] = xor3(acc[j], __builtin_amdgcn_alignbit(win[q][j + 1], win[q][j], shs[q]),
+                      __builtin_amdgcn_alignbit(win[q + 1][j + 1], win[q + 1][j], shs[q + 1]));
+  };
+#pragma unroll
+  for (int c = 0; c < NREG; ++c) {
+    const int cnt = (NIDX - 64 * c) < 64 ? (NIDX - 64 * c) : 64;
+    const int half = (cnt + 1) / 2;
+    const uint32_t hi = half == 32
+                            ? halves(shreg[c]).hi
+                            : (uint32_t)__builtin_amdgcn_ds_bpermute((lane + half) << 2, (int)shreg[c]);
+    const uint32_t pk = shreg[c] | hi << 16;
+    uint32_t wa[U][G::R + 1], wb[U][G::R + 1], sa[U], sb[U];
+    int kk = 0;
+    if (cnt >= U) load(wa, sa, pk, 0);
+    // invariant at the top: wa holds group kk when kk + U <= cnt
+    for (; kk + 2 * U <= cnt; kk += 2 * U) {
+      load(wb, sb, pk, kk + U);
+      combine(wa, sa);
+      if (kk + 3 * U <= cnt) load(wa, sa, pk, kk + 2 * U);
+      combine(wb, sb);
+    }
+    if (kk + U <= cnt) {
+      combine(wa, sa);
+      kk += U;
+    }
+    for (; kk < cnt; ++kk) {
+      uint32_t win[G::R + 1];
+      const uint32_t sh = slot(pk, kk);
+#pragma unroll
+      for (int j = 0; j <= G::R; ++j) win[j] = u2[L::window(lane, sh, j)];
+#pragma unroll
+      for (int j = 0; j < G::R; ++j) acc[j] ^= __builtin_amdgcn_alignbit(win[j + 1], win[j], sh);
+    }
+  }
+}
+
 // acc = the lane's R dwords of a * (sum over the support of X^index)
 template <int ID, int N, bool PIPE = false>
 __device__ __forceinline__ void sparse_product(const uint32_t *u2,
